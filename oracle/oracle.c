@@ -1,0 +1,267 @@
+/*
+ * oracle.c -- TEST INFRASTRUCTURE ONLY: a plain, slow, obviously correct
+ * complex128 state-vector simulator. It exists to check the HIP path against
+ * the definitions, never to serve results: only the test suite, the smoke
+ * check and the benchmark's CPU-baseline leg may load it.
+ *
+ * It shares no code with the HIP library. Every function follows a definition
+ * written out from the paper (Sec. II: a state vector holds all 2^n complex
+ * amplitudes and a gate updates it; Sec. III-B: simulate once, then sample
+ * the terminal measurement and evaluate expectation values on the cached
+ * state) and the textbook mathematics the paper leaves implicit.
+ *
+ * Conventions (the paper takes Qiskit / OpenQASM2 circuits, Sec. III-A, so
+ * Qiskit's are used): qubit q is bit q of the amplitude index (little-endian);
+ * in a k-qubit matrix U the row/column bit j belongs to targets[j]; gate
+ * matrices are Qiskit's, global phase included.
+ *
+ * Build: gcc -O2 -fPIC -shared -std=c11 -fcx-limited-range oracle.c -o liboracle.so -lm
+ * (-fcx-limited-range only drops C99 Annex G's NaN/Inf recovery in complex
+ *  multiplication; finite products are the plain (ac-bd) + i(ad+bc).)
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef double complex cplx;
+
+/* ------------------------------------------------------------------ gates */
+
+/* Writes the 2^k x 2^k row-major matrix of the named gate acting on its
+ * TARGET qubits, and says how many leading qubits of the op are controls.
+ * cx/cy/cz/cp: qubits = (control, target); ccx: (control, control, target).
+ * swap and rzz act on both qubits as targets.
+ * Returns k (number of targets), or -1 for an unknown name. */
+int or_gate_matrix(const char *name, const double *p, cplx *U, int *ncontrols)
+{
+    const double r2 = 1.0 / sqrt(2.0);
+    *ncontrols = 0;
+    memset(U, 0, 16 * sizeof(cplx));
+#define SET2(a, b, c, d) (U[0] = (a), U[1] = (b), U[2] = (c), U[3] = (d))
+    if (!strcmp(name, "h")) { SET2(r2, r2, r2, -r2); return 1; }
+    if (!strcmp(name, "x")) { SET2(0, 1, 1, 0); return 1; }
+    if (!strcmp(name, "y")) { SET2(0, -I, I, 0); return 1; }
+    if (!strcmp(name, "z")) { SET2(1, 0, 0, -1); return 1; }
+    if (!strcmp(name, "s")) { SET2(1, 0, 0, I); return 1; }
+    if (!strcmp(name, "sdg")) { SET2(1, 0, 0, -I); return 1; }
+    if (!strcmp(name, "t")) { SET2(1, 0, 0, cexp(I * M_PI / 4)); return 1; }
+    if (!strcmp(name, "tdg")) { SET2(1, 0, 0, cexp(-I * M_PI / 4)); return 1; }
+    /* sqrt(X) = 1/2 [[1+i, 1-i], [1-i, 1+i]] */
+    if (!strcmp(name, "sx")) { SET2(0.5 * (1 + I), 0.5 * (1 - I), 0.5 * (1 - I), 0.5 * (1 + I)); return 1; }
+    if (!strcmp(name, "rx")) {
+        double c = cos(p[0] / 2), s = sin(p[0] / 2);
+        SET2(c, -I * s, -I * s, c); return 1;
+    }
+    if (!strcmp(name, "ry")) {
+        double c = cos(p[0] / 2), s = sin(p[0] / 2);
+        SET2(c, -s, s, c); return 1;
+    }
+    if (!strcmp(name, "rz")) { SET2(cexp(-I * p[0] / 2), 0, 0, cexp(I * p[0] / 2)); return 1; }
+    if (!strcmp(name, "p")) { SET2(1, 0, 0, cexp(I * p[0])); return 1; }
+    if (!strcmp(name, "u3")) {
+        double c = cos(p[0] / 2), s = sin(p[0] / 2);
+        SET2(c, -cexp(I * p[2]) * s, cexp(I * p[1]) * s, cexp(I * (p[1] + p[2])) * c);
+        return 1;
+    }
+    if (!strcmp(name, "cx")) { *ncontrols = 1; SET2(0, 1, 1, 0); return 1; }
+    if (!strcmp(name, "cy")) { *ncontrols = 1; SET2(0, -I, I, 0); return 1; }
+    if (!strcmp(name, "cz")) { *ncontrols = 1; SET2(1, 0, 0, -1); return 1; }
+    if (!strcmp(name, "cp")) { *ncontrols = 1; SET2(1, 0, 0, cexp(I * p[0])); return 1; }
+    if (!strcmp(name, "ccx")) { *ncontrols = 2; SET2(0, 1, 1, 0); return 1; }
+    if (!strcmp(name, "swap")) {
+        /* basis |q1 q0>: 00->00, 01->10, 10->01, 11->11 */
+        U[0 * 4 + 0] = 1; U[1 * 4 + 2] = 1; U[2 * 4 + 1] = 1; U[3 * 4 + 3] = 1;
+        return 2;
+    }
+    if (!strcmp(name, "rzz")) {
+        /* exp(-i g/2 Z(x)Z): phase exp(-i g/2) where both bits agree, exp(+i g/2) otherwise */
+        cplx a = cexp(-I * p[0] / 2), b = cexp(I * p[0] / 2);
+        U[0] = a; U[5] = b; U[10] = b; U[15] = a;
+        return 2;
+    }
+#undef SET2
+    return -1;
+}
+
+/* --------------------------------------------------------------- applying */
+
+/* Applies the 2^k x 2^k matrix U to the target qubits of psi, on the subspace
+ * where every control qubit is 1 (Sec. II's state-vector update). For every
+ * index i whose target bits are all 0 and control bits all 1, the 2^k
+ * amplitudes i + sum_j bit_j(m) 2^targets[j] (m < 2^k) are gathered into v,
+ * w = U v is formed with the sum over m in order, and w is written back. */
+void or_apply_matrix(cplx *psi, int n, const cplx *U, int k,
+                     const int *targets, const int *controls, int nc)
+{
+    const uint64_t N = 1ull << n;
+    const int K = 1 << k;
+    uint64_t tmask = 0, cmask = 0;
+    for (int j = 0; j < k; j++) tmask |= 1ull << targets[j];
+    for (int j = 0; j < nc; j++) cmask |= 1ull << controls[j];
+    uint64_t idx[32];
+    cplx v[32];
+    for (uint64_t i = 0; i < N; i++) {
+        if ((i & tmask) != 0) continue;
+        if ((i & cmask) != cmask) continue;
+        for (int m = 0; m < K; m++) {
+            uint64_t a = i;
+            for (int j = 0; j < k; j++)
+                if ((m >> j) & 1) a |= 1ull << targets[j];
+            idx[m] = a;
+            v[m] = psi[a];
+        }
+        for (int r = 0; r < K; r++) {
+            cplx w = 0;
+            for (int m = 0; m < K; m++) w += U[r * K + m] * v[m];
+            psi[idx[r]] = w;
+        }
+    }
+}
+
+/* Applies a named gate (or its adjoint, U^dagger, when `adjoint` is set). */
+int or_apply_op(cplx *psi, int n, const char *name, const int *qubits,
+                const double *params, int adjoint)
+{
+    cplx U[16], A[16];
+    int nc;
+    int k = or_gate_matrix(name, params, U, &nc);
+    if (k < 0) return -1;
+    int K = 1 << k;
+    if (adjoint) {
+        for (int r = 0; r < K; r++)
+            for (int c = 0; c < K; c++) A[r * K + c] = conj(U[c * K + r]);
+        memcpy(U, A, sizeof(cplx) * K * K);
+    }
+    or_apply_matrix(psi, n, U, k, qubits + nc, qubits, nc);
+    return 0;
+}
+
+/* psi <- |basis> */
+void or_init_basis(cplx *psi, int n, uint64_t basis)
+{
+    const uint64_t N = 1ull << n;
+    for (uint64_t i = 0; i < N; i++) psi[i] = 0;
+    psi[basis] = 1;
+}
+
+/* --------------------------------------------------------- summation, RNG */
+
+/* Neumaier's improved Kahan summation: the running sum s plus a correction c
+ * that collects the rounding error of every addition. */
+typedef struct { double s, c; } neum;
+
+static void neum_add(neum *a, double x)
+{
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x;
+    else a->c += (x - t) + a->s;
+    a->s = t;
+}
+
+static double neum_value(const neum *a) { return a->s + a->c; }
+
+/* SplitMix64 (Steele, Lea, Flood, "Fast splittable pseudorandom number
+ * generators", OOPSLA 2014): the state advances by the golden-ratio gamma
+ * 0x9E3779B97F4A7C15 and each output is the state passed through the
+ * variant-13 64-bit finaliser (xor-shift 30, multiply 0xBF58476D1CE4E5B9,
+ * xor-shift 27, multiply 0x94D049BB133111EB, xor-shift 31). The s-th output
+ * (s from 0) of the generator seeded with `seed` is therefore the finaliser of
+ * seed + (s+1)*gamma, which makes it a counter-based generator. */
+uint64_t or_splitmix64(uint64_t seed, uint64_t s)
+{
+    uint64_t z = seed + (s + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* Uniform double in [0,1) from the top 53 bits of the s-th output. */
+double or_u01(uint64_t seed, uint64_t s)
+{
+    return (double)(or_splitmix64(seed, s) >> 11) * 0x1.0p-53;
+}
+
+/* ------------------------------------------------------------ measurement */
+
+/* Squared norm sum_i |psi_i|^2 with Neumaier summation in index order. */
+double or_norm2(const cplx *psi, int n)
+{
+    const uint64_t N = 1ull << n;
+    neum a = {0, 0};
+    for (uint64_t i = 0; i < N; i++) {
+        double re = creal(psi[i]), im = cimag(psi[i]);
+        neum_add(&a, re * re + im * im);
+    }
+    return neum_value(&a);
+}
+
+/* Cumulative distribution F(i) = sum_{j<=i} |psi_j|^2 with Neumaier
+ * summation in index order. F is made non-decreasing by keeping the running
+ * maximum (the exact prefix sums are non-decreasing; the compensated value can
+ * dip by an ulp when a term is below the ulp of the sum). */
+void or_cdf(const cplx *psi, int n, double *F)
+{
+    const uint64_t N = 1ull << n;
+    neum a = {0, 0};
+    double prev = 0;
+    for (uint64_t i = 0; i < N; i++) {
+        double re = creal(psi[i]), im = cimag(psi[i]);
+        neum_add(&a, re * re + im * im);
+        double f = neum_value(&a);
+        if (f < prev) f = prev;
+        F[i] = prev = f;
+    }
+}
+
+/* Terminal measurement of every qubit, `shots` times (Sec. III-B: the state is
+ * simulated once and the shots are drawn from it). Shot s draws
+ * u = U01(seed, s), sets r = u * F(N-1) and returns the smallest i with
+ * F(i) > r; if rounding leaves none, the largest i with nonzero probability.
+ * F is caller scratch of 2^n doubles. */
+void or_sample(const cplx *psi, int n, int64_t shots, uint64_t seed,
+               uint64_t *out, double *F)
+{
+    const uint64_t N = 1ull << n;
+    or_cdf(psi, n, F);
+    double total = F[N - 1];
+    uint64_t last_nonzero = 0;
+    for (uint64_t i = 0; i < N; i++)
+        if (creal(psi[i]) != 0 || cimag(psi[i]) != 0) last_nonzero = i;
+    for (int64_t s = 0; s < shots; s++) {
+        double r = or_u01(seed, (uint64_t)s) * total;
+        /* binary search for the first F(i) > r */
+        uint64_t lo = 0, hi = N; /* answer in [lo, hi]; hi = N means none */
+        while (lo < hi) {
+            uint64_t mid = lo + (hi - lo) / 2;
+            if (F[mid] > r) hi = mid;
+            else lo = mid + 1;
+        }
+        out[s] = (lo < N) ? lo : last_nonzero;
+    }
+}
+
+/* Expectation value of the Pauli string P = i^{nY} X^x Z^z, where x and z are
+ * qubit bitmasks (a Y on qubit q sets bit q in both; nY = popcount(x & z)):
+ * P|b> = i^{nY} (-1)^{popcount(b & z)} |b xor x>, so
+ * <psi|P|psi> = sum_b conj(psi_{b^x}) psi_b i^{nY} (-1)^{popcount(b&z)},
+ * divided by ||psi||^2 (Sec. III-B: evaluated on the cached state).
+ * Real and imaginary parts are Neumaier sums in index order. */
+void or_expect(const cplx *psi, int n, uint64_t xmask, uint64_t zmask,
+               double *re_out, double *im_out)
+{
+    const uint64_t N = 1ull << n;
+    int ny = __builtin_popcountll(xmask & zmask) & 3;
+    cplx iny = (ny == 0) ? 1 : (ny == 1) ? I : (ny == 2) ? -1 : -I;
+    neum sr = {0, 0}, si = {0, 0};
+    for (uint64_t b = 0; b < N; b++) {
+        double sign = (__builtin_popcountll(b & zmask) & 1) ? -1.0 : 1.0;
+        cplx t = conj(psi[b ^ xmask]) * psi[b] * iny * sign;
+        neum_add(&sr, creal(t));
+        neum_add(&si, cimag(t));
+    }
+    double nrm = or_norm2(psi, n);
+    *re_out = neum_value(&sr) / nrm;
+    *im_out = neum_value(&si) / nrm;
+}

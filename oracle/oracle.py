@@ -1,0 +1,194 @@
+"""TEST INFRASTRUCTURE ONLY -- Python face of the plain complex128 oracle.
+
+Loads ``liboracle.so`` (built from ``oracle.c`` by ``build_oracle()``) and wraps
+it for numpy arrays. Only the tests, the smoke check and the benchmark's
+CPU-baseline leg use this module; the HIP library never imports or links it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_c_cplx_p = ctypes.c_void_p
+
+
+def build_oracle(force: bool = True) -> str:
+    """Compile oracle.c with gcc (-O2, no fast-math) into liboracle.so."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-std=gnu11",
+                               "-fcx-limited-range", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build_oracle(force=True)
+        L = ctypes.CDLL(_LIB)
+        L.or_gate_matrix.argtypes = [ctypes.c_char_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.POINTER(ctypes.c_int)]
+        L.or_gate_matrix.restype = ctypes.c_int
+        L.or_apply_matrix.argtypes = [_c_cplx_p, ctypes.c_int, _c_cplx_p, ctypes.c_int,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+        L.or_apply_matrix.restype = None
+        L.or_apply_op.argtypes = [_c_cplx_p, ctypes.c_int, ctypes.c_char_p, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_int]
+        L.or_apply_op.restype = ctypes.c_int
+        L.or_init_basis.argtypes = [_c_cplx_p, ctypes.c_int, ctypes.c_uint64]
+        L.or_init_basis.restype = None
+        L.or_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        L.or_splitmix64.restype = ctypes.c_uint64
+        L.or_u01.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        L.or_u01.restype = ctypes.c_double
+        L.or_norm2.argtypes = [_c_cplx_p, ctypes.c_int]
+        L.or_norm2.restype = ctypes.c_double
+        L.or_cdf.argtypes = [_c_cplx_p, ctypes.c_int, ctypes.c_void_p]
+        L.or_cdf.restype = None
+        L.or_sample.argtypes = [_c_cplx_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64,
+                                ctypes.c_void_p, ctypes.c_void_p]
+        L.or_sample.restype = None
+        L.or_expect.argtypes = [_c_cplx_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+        L.or_expect.restype = None
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check_state(psi: np.ndarray) -> int:
+    if psi.dtype != np.complex128 or not psi.flags.c_contiguous:
+        raise TypeError("oracle states are C-contiguous complex128 arrays")
+    n = int(psi.size).bit_length() - 1
+    if psi.size != (1 << n):
+        raise ValueError("state length must be a power of two")
+    return n
+
+
+def gate_matrix(name: str, params=()):
+    """(U, k, ncontrols) of a named gate; U acts on the target qubits."""
+    U = np.zeros(16, dtype=np.complex128)
+    p = np.zeros(3, dtype=np.float64)
+    p[: len(params)] = params
+    nc = ctypes.c_int(0)
+    k = lib().or_gate_matrix(name.encode(), _ptr(p), _ptr(U), ctypes.byref(nc))
+    if k < 0:
+        raise ValueError("unknown gate %r" % name)
+    K = 1 << k
+    return U[: K * K].reshape(K, K).copy(), k, nc.value
+
+
+def basis_state(n: int, basis: int = 0) -> np.ndarray:
+    psi = np.empty(1 << n, dtype=np.complex128)
+    lib().or_init_basis(_ptr(psi), n, int(basis))
+    return psi
+
+
+def apply_matrix(psi: np.ndarray, U, targets, controls=()):
+    n = _check_state(psi)
+    U = np.ascontiguousarray(np.asarray(U, dtype=np.complex128))
+    k = len(targets)
+    if U.shape != (1 << k, 1 << k):
+        raise ValueError("U shape does not match the number of targets")
+    t = np.asarray(targets, dtype=np.int32)
+    c = np.asarray(controls if len(controls) else [0], dtype=np.int32)
+    lib().or_apply_matrix(_ptr(psi), n, _ptr(U), k, _ptr(t), _ptr(c), len(controls))
+    return psi
+
+
+def apply_op(psi: np.ndarray, op, adjoint: bool = False):
+    name, qubits, params = op
+    n = _check_state(psi)
+    q = np.asarray(qubits, dtype=np.int32)
+    p = np.zeros(3, dtype=np.float64)
+    p[: len(params)] = params
+    if lib().or_apply_op(_ptr(psi), n, name.encode(), _ptr(q), _ptr(p), int(adjoint)) != 0:
+        raise ValueError("unknown gate %r" % name)
+    return psi
+
+
+def run(ops, n: int, basis: int = 0, psi: np.ndarray | None = None):
+    """Simulate a gate list from |basis> (or from a given state, in place)."""
+    if psi is None:
+        psi = basis_state(n, basis)
+    for op in ops:
+        apply_op(psi, op)
+    return psi
+
+
+def run_inverse(ops, psi: np.ndarray):
+    """Apply the inverse circuit: the list reversed, every gate adjoint."""
+    for op in reversed(ops):
+        apply_op(psi, op, adjoint=True)
+    return psi
+
+
+def splitmix64(seed: int, s: int) -> int:
+    return int(lib().or_splitmix64(seed & (2**64 - 1), s))
+
+
+def u01(seed: int, s: int) -> float:
+    return float(lib().or_u01(seed & (2**64 - 1), s))
+
+
+def norm2(psi: np.ndarray) -> float:
+    n = _check_state(psi)
+    return float(lib().or_norm2(_ptr(psi), n))
+
+
+def cdf(psi: np.ndarray) -> np.ndarray:
+    n = _check_state(psi)
+    F = np.empty(psi.size, dtype=np.float64)
+    lib().or_cdf(_ptr(psi), n, _ptr(F))
+    return F
+
+
+def sample(psi: np.ndarray, shots: int, seed: int) -> np.ndarray:
+    n = _check_state(psi)
+    out = np.empty(shots, dtype=np.uint64)
+    F = np.empty(psi.size, dtype=np.float64)
+    lib().or_sample(_ptr(psi), n, int(shots), seed & (2**64 - 1), _ptr(out), _ptr(F))
+    return out
+
+
+def expect(psi: np.ndarray, xmask: int, zmask: int):
+    """Complex <P> for P = i^{nY} X^x Z^z (divided by the squared norm)."""
+    n = _check_state(psi)
+    re = ctypes.c_double()
+    im = ctypes.c_double()
+    lib().or_expect(_ptr(psi), n, int(xmask), int(zmask), ctypes.byref(re), ctypes.byref(im))
+    return complex(re.value, im.value)
+
+
+def expect_terms(psi: np.ndarray, terms):
+    """Real parts of <P_t> for terms (xmask, zmask, coeff), and sum coeff*<P_t>."""
+    vals = np.array([expect(psi, x, z).real for x, z, _ in terms], dtype=np.float64)
+    coeff = np.array([c for _, _, c in terms], dtype=np.float64)
+    return vals, float(np.sum(coeff * vals))
+
+
+def pauli_masks(label: str):
+    """Masks of a Pauli label written qubit 0 first, e.g. 'XIZY' -> X on 0,
+    Z on 2, Y on 3."""
+    x = z = 0
+    for q, ch in enumerate(label):
+        if ch in "XY":
+            x |= 1 << q
+        if ch in "ZY":
+            z |= 1 << q
+        if ch not in "IXYZ":
+            raise ValueError(label)
+    return x, z

@@ -1,0 +1,351 @@
+"""Pins of the complex128 oracle against things other than itself: closed forms,
+invariants, library routines, brute force and published values. CPU only."""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.stats
+
+import workloads as W
+from oracle import fullmatrix as FM
+
+# textbook Pauli matrices in the computational basis (|0> = (1,0))
+I2 = np.eye(2, dtype=np.complex128)
+PX = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+PY = np.array([[0, -1j], [1j, 0]], dtype=np.complex128)
+PZ = np.array([[1, 0], [0, -1]], dtype=np.complex128)
+
+
+def rand_unitary(rng, K):
+    A = rng.normal(size=(K, K)) + 1j * rng.normal(size=(K, K))
+    Q, R = np.linalg.qr(A)
+    return Q * (np.diag(R) / np.abs(np.diag(R)))
+
+
+def mat(O, name, *params):
+    return O.gate_matrix(name, params)[0]
+
+
+# ---------------------------------------------------------------- the embedding itself
+
+def test_embed_little_endian_cnot():
+    # control qubit 0, target qubit 1: |q1 q0> = |01> (index 1) <-> |11> (index 3)
+    G = FM.gate_full(PX, [1], [0], 2)
+    P = np.zeros((4, 4))
+    P[0, 0] = P[2, 2] = 1
+    P[3, 1] = P[1, 3] = 1
+    assert np.array_equal(G, P)
+
+
+def test_embed_kron_order():
+    rng = np.random.default_rng(1)
+    G = rand_unitary(rng, 2)
+    assert np.allclose(FM.embed(G, [0], 2), np.kron(I2, G))
+    assert np.allclose(FM.embed(G, [1], 2), np.kron(G, I2))
+    G4 = rand_unitary(rng, 4)
+    S = FM.embed(np.eye(4)[[0, 2, 1, 3]], [0, 1], 2)   # qubit exchange
+    assert np.allclose(FM.embed(G4, [1, 0], 2), S @ G4 @ S)
+    assert np.allclose(FM.embed(G, [2], 3), np.kron(G, np.eye(4)))
+
+
+# -------------------------------------------------------------- indexing vs brute force
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6])
+def test_apply_matrix_matches_embedding_all_columns(O, n):
+    rng = np.random.default_rng(100 + n)
+    for trial in range(12):
+        k = int(rng.integers(1, min(n, 3) + 1))
+        nc = int(rng.integers(0, min(n - k, 2) + 1))
+        qs = rng.choice(n, size=k + nc, replace=False)
+        t, c = list(qs[:k]), list(qs[k:])
+        U = rand_unitary(rng, 1 << k)
+        full = FM.gate_full(U, t, c, n)
+        for b in range(1 << n):          # every basis input: every column
+            psi = O.basis_state(n, b)
+            O.apply_matrix(psi, U, t, c)
+            assert np.max(np.abs(psi - full[:, b])) <= 1e-13
+
+
+@pytest.mark.parametrize("n", [3, 4, 5])
+def test_named_gate_circuits_match_embedding(O, n):
+    ops = W.random_circuit(n, 60, seed=7 + n)
+    Uc = FM.circuit_unitary(ops, n, lambda name, p: O.gate_matrix(name, p))
+    rng = np.random.default_rng(n)
+    v = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    psi = v.copy()
+    O.run(ops, n, psi=psi)
+    assert np.max(np.abs(psi - Uc @ v)) <= 1e-12
+
+
+# ---------------------------------------------------------------- gate conventions
+
+def test_pauli_algebra(O):
+    X, Y, Z = mat(O, "x"), mat(O, "y"), mat(O, "z")
+    assert np.array_equal(X, PX) and np.array_equal(Z, PZ)   # X|0>=|1>, Z|0>=|0>
+    for P in (X, Y, Z):
+        assert np.allclose(P @ P, I2)
+    assert np.allclose(X @ Y, 1j * Z)                         # fixes the sign of Y
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.3, 1.7, math.pi, 4.4, 2 * math.pi - 0.1])
+def test_rotations_are_exponentials(O, theta):
+    assert np.allclose(mat(O, "rx", theta), scipy.linalg.expm(-0.5j * theta * PX), atol=1e-15)
+    assert np.allclose(mat(O, "ry", theta), scipy.linalg.expm(-0.5j * theta * PY), atol=1e-15)
+    assert np.allclose(mat(O, "rz", theta), scipy.linalg.expm(-0.5j * theta * PZ), atol=1e-15)
+    zz = np.kron(PZ, PZ)
+    assert np.allclose(mat(O, "rzz", theta), scipy.linalg.expm(-0.5j * theta * zz), atol=1e-15)
+    # the phase gate is RZ up to the global phase exp(i theta/2)
+    assert np.allclose(mat(O, "p", theta), np.exp(0.5j * theta) * mat(O, "rz", theta), atol=1e-15)
+
+
+def test_fixed_gate_relations(O):
+    H, S, T, X, Z = (mat(O, g) for g in ("h", "s", "t", "x", "z"))
+    assert np.allclose(H, (PX + PZ) / math.sqrt(2))
+    assert np.allclose(S @ S, Z) and np.allclose(T @ T, S)
+    assert np.allclose(mat(O, "sdg"), S.conj().T) and np.allclose(mat(O, "tdg"), T.conj().T)
+    sx = mat(O, "sx")
+    assert np.allclose(sx @ sx, X)
+    assert np.allclose(sx, H @ S @ H)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_u3_special_cases(O, seed):
+    th, lam = np.random.default_rng(seed).uniform(0, 2 * math.pi, 2)
+    u3 = lambda a, b, c: mat(O, "u3", a, b, c)  # noqa: E731
+    assert np.allclose(u3(th, -math.pi / 2, math.pi / 2), mat(O, "rx", th))
+    assert np.allclose(u3(th, 0, 0), mat(O, "ry", th))
+    assert np.allclose(u3(math.pi / 2, 0, math.pi), mat(O, "h"))
+    assert np.allclose(u3(0, 0, lam), mat(O, "p", lam))
+    # U3(th, phi, lam) = RZ(phi) RY(th) RZ(lam) up to the phase exp(i(phi+lam)/2)
+    phi = 0.77 * seed + 0.1
+    want = np.exp(0.5j * (phi + lam)) * mat(O, "rz", phi) @ mat(O, "ry", th) @ mat(O, "rz", lam)
+    assert np.allclose(u3(th, phi, lam), want)
+
+
+def test_two_qubit_gate_relations(O):
+    n = 2
+    mf = lambda name, p: O.gate_matrix(name, p)  # noqa: E731
+    full = lambda ops: FM.circuit_unitary(ops, n, mf)  # noqa: E731
+    cx01 = full([("cx", (0, 1), ())])
+    cz = full([("cz", (0, 1), ())])
+    h1 = full([("h", (1,), ())])
+    assert np.allclose(cx01, h1 @ cz @ h1)
+    assert np.allclose(full([("cz", (0, 1), ())]), full([("cz", (1, 0), ())]))
+    assert np.allclose(cz, full([("cp", (0, 1), (math.pi,))]))
+    swap = full([("swap", (0, 1), ())])
+    three = full([("cx", (0, 1), ()), ("cx", (1, 0), ()), ("cx", (0, 1), ())])
+    assert np.allclose(swap, three)
+    cy = full([("cy", (0, 1), ())])
+    sdg1, s1 = full([("sdg", (1,), ())]), full([("s", (1,), ())])
+    assert np.allclose(cy, s1 @ cx01 @ sdg1)
+    # ccx: flips the target exactly on the two basis states with both controls set
+    ccx = FM.circuit_unitary([("ccx", (0, 1, 2), ())], 3, mf)
+    perm = np.eye(8)[[0, 1, 2, 7, 4, 5, 6, 3]]
+    assert np.array_equal(ccx, perm)
+
+
+# ------------------------------------------------------------------- closed forms
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 12])
+def test_ghz_closed_form(O, n):
+    psi = O.run(W.ghz(n), n)
+    want = np.zeros(1 << n, dtype=np.complex128)
+    want[0] = want[-1] = 1 / math.sqrt(2)
+    assert np.max(np.abs(psi - want)) <= 1e-15
+
+
+def qft_closed_form(n, x):
+    y = np.arange(1 << n, dtype=np.uint64)
+    ph = ((np.uint64(x) * y) & np.uint64((1 << n) - 1)).astype(np.float64) / float(1 << n)
+    return np.exp(2j * np.pi * ph) / math.sqrt(1 << n)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 6, 9, 12])
+def test_qft_closed_form(O, n):
+    for seed in range(3):
+        x = W.random_basis_state(n, seed)
+        psi = O.run(W.qft(n), n, basis=x)
+        assert np.max(np.abs(psi - qft_closed_form(n, x))) <= 1e-12
+
+
+def test_qft_is_the_dft_matrix(O):
+    n = 5
+    Uq = FM.circuit_unitary(W.qft(n), n, lambda name, p: O.gate_matrix(name, p))
+    N = 1 << n
+    dft = np.conj(scipy.linalg.dft(N)) / math.sqrt(N)   # scipy's dft uses exp(-2 pi i jk/N)
+    assert np.allclose(Uq, dft, atol=1e-13)
+
+
+# --------------------------------------------------------------------- invariants
+
+@pytest.mark.parametrize("n", [4, 8, 11])
+def test_mirror_returns_to_zero_and_norm_is_kept(O, n):
+    ops = W.random_circuit(n, 150, seed=n)
+    psi = O.run(ops, n)
+    assert abs(O.norm2(psi) - 1.0) <= 1e-13
+    O.run_inverse(ops, psi)
+    assert 1.0 - abs(psi[0]) ** 2 <= 1e-12
+    ops = W.brickwork(n, 6, seed=3)
+    psi = O.run(ops, n)
+    O.run_inverse(ops, psi)
+    assert 1.0 - abs(psi[0]) ** 2 <= 1e-12
+
+
+# ------------------------------------------------------------------- the generator
+
+def _golden_splitmix():
+    path = os.path.join(os.path.dirname(__file__), "golden", "splitmix64_seed0.txt")
+    return [int(line, 16) for line in open(path) if line.strip() and not line.startswith("#")]
+
+
+def test_splitmix64_published_outputs(O):
+    want = _golden_splitmix()
+    assert [O.splitmix64(0, s) for s in range(len(want))] == want
+    # the counter form equals the sequential generator seeded at `seed`
+    assert O.splitmix64(0x1234, 5) == O.splitmix64((0x1234 + 5 * 0x9E3779B97F4A7C15) % 2**64, 0)
+
+
+def test_u01_is_uniform(O):
+    u = np.array([O.u01(99, s) for s in range(200000)])
+    assert u.min() >= 0.0 and u.max() < 1.0
+    assert scipy.stats.kstest(u, "uniform").pvalue > 1e-4
+    assert O.u01(0, 0) == (0xe220a8397b1dcdaf >> 11) * 2.0 ** -53
+
+
+# -------------------------------------------------------------------- the sampler
+
+def test_sampler_basis_state(O):
+    n = 7
+    psi = O.basis_state(n, 77)
+    assert np.all(O.sample(psi, 500, seed=3) == 77)
+
+
+def test_sampler_ghz_binomial(O):
+    n, S = 10, 4096
+    psi = O.run(W.ghz(n), n)
+    out = O.sample(psi, S, seed=11)
+    assert set(np.unique(out)) <= {0, (1 << n) - 1}
+    c0 = int(np.sum(out == 0))
+    assert abs(c0 - S / 2) <= 2.5 * math.sqrt(S)
+
+
+def test_sampler_total_variation_bound(O):
+    # E[TV] <= 1/2 sqrt((K-1)/S); McDiarmid adds sqrt(ln(1/delta)/(2S)), delta=1e-6
+    n, S = 6, 20000
+    psi = O.run(W.brickwork(n, 6, seed=5), n)
+    p = np.abs(psi) ** 2
+    out = O.sample(psi, S, seed=12)
+    h = np.bincount(out.astype(np.int64), minlength=1 << n) / S
+    tv = 0.5 * np.sum(np.abs(h - p))
+    K = 1 << n
+    assert tv <= 0.5 * math.sqrt((K - 1) / S) + math.sqrt(math.log(1e6) / (2 * S))
+
+
+def test_sampler_is_inverse_cdf_of_probabilities(O):
+    # the outcome of shot s is the index whose probability interval holds u_s
+    # (the intervals come from numpy's cumulative sum, not the oracle's CDF)
+    n = 5
+    psi = O.run(W.random_circuit(n, 40, seed=9), n)
+    p = np.abs(psi) ** 2
+    edges = np.concatenate([[0.0], np.cumsum(p)])
+    out = O.sample(psi, 3000, seed=21)
+    for s, o in enumerate(out):
+        r = O.u01(21, s) * edges[-1]
+        assert edges[o] - 1e-12 <= r < edges[o + 1] + 1e-12
+
+
+def test_hellinger_sampling_law(O):
+    # Sec. IV-C: for support K and S shots the Bhattacharyya coefficient of the
+    # empirical distribution falls as 1 - (K-1)/(8S). Uniform support of K=16.
+    n, S, trials = 4, 400, 300
+    psi = O.run([("h", (q,), ()) for q in range(n)], n)
+    K = 1 << n
+    defects = []
+    for t in range(trials):
+        out = O.sample(psi, S, seed=1000 + t)
+        h = np.bincount(out.astype(np.int64), minlength=K) / S
+        defects.append(1.0 - np.sum(np.sqrt(h / K)))
+    mean = float(np.mean(defects))
+    assert abs(mean - (K - 1) / (8 * S)) <= 0.15 * (K - 1) / (8 * S)
+
+
+# --------------------------------------------------------------- expectation values
+
+def pauli_full(label):
+    """Dense operator of a Pauli label written qubit 0 first (textbook kron)."""
+    mats = {"I": I2, "X": PX, "Y": PY, "Z": PZ}
+    M = np.array([[1.0 + 0j]])
+    for ch in label:                 # qubit q ends up on bit q: kron(new, old)
+        M = np.kron(mats[ch], M)
+    return M
+
+
+def test_expect_matches_dense_pauli_operator(O):
+    n = 5
+    rng = np.random.default_rng(4)
+    psi = O.run(W.random_circuit(n, 80, seed=4), n)
+    for _ in range(60):
+        label = "".join(rng.choice(list("IXYZ"), size=n))
+        x, z = O.pauli_masks(label)
+        want = np.vdot(psi, pauli_full(label) @ psi)
+        got = O.expect(psi, x, z)
+        assert abs(got - want) <= 1e-13
+
+
+def test_expect_special_cases(O):
+    n = 6
+    b = 0b101100
+    psi = O.basis_state(n, b)
+    for u in range(n):
+        for v in range(u + 1, n):
+            e = O.expect(psi, 0, (1 << u) | (1 << v))
+            assert e == (-1.0) ** (((b >> u) ^ (b >> v)) & 1)
+    plus = O.run([("h", (q,), ()) for q in range(n)], n)
+    for q in range(n):
+        assert abs(O.expect(plus, 1 << q, 0) - 1) <= 1e-15
+        assert abs(O.expect(plus, 0, 1 << q)) <= 1e-15
+        assert abs(O.expect(plus, 1 << q, 1 << q)) <= 1e-15
+    g = O.run(W.ghz(n), n)
+    assert abs(O.expect(g, 0, 0b11) - 1) <= 1e-15
+    assert abs(O.expect(g, (1 << n) - 1, 0) - 1) <= 1e-15
+    for th in (0.1, 1.3, 2.9):
+        s = O.run([("ry", (0,), (th,))], 1)
+        assert abs(O.expect(s, 0, 1) - math.cos(th)) <= 1e-15
+        assert abs(O.expect(s, 1, 0) - math.sin(th)) <= 1e-15
+    yplus = O.run([("h", (0,), ()), ("s", (0,), ())], 1)
+    assert abs(O.expect(yplus, 1, 1) - 1) <= 1e-15
+
+
+def qaoa_p1_edge_zz(gamma, beta, edges, n):
+    """<Z_u Z_v> after one QAOA layer RZZ(gamma) on the edges, RX(beta) on every
+    qubit, from |+>^n: the closed form of Wang, Hadfield, Jiang, Rieffel,
+    PRA 97, 022304 (2018) for <C_uv>, C_uv = (1 - Z_u Z_v)/2, in their
+    parametrisation exp(-i g C) exp(-i b B), i.e. g = -gamma, b = beta/2."""
+    g, b = -gamma, beta / 2
+    adj = [set() for _ in range(n)]
+    for u, v in edges:
+        adj[u].add(v)
+        adj[v].add(u)
+    out = []
+    for u, v in edges:
+        d, e = len(adj[u]) - 1, len(adj[v]) - 1
+        f = len(adj[u] & adj[v])
+        c = 0.5 + 0.25 * math.sin(4 * b) * math.sin(g) * (math.cos(g) ** d + math.cos(g) ** e) \
+            - 0.25 * math.sin(2 * b) ** 2 * math.cos(g) ** (d + e - 2 * f) * (1 - math.cos(2 * g) ** f)
+        out.append(1 - 2 * c)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_qaoa_p1_closed_form(O, seed):
+    n = 10
+    ops, edges, terms = W.qaoa_maxcut(n, 1, seed)
+    gamma = ops[n][2][0]
+    beta = ops[-1][2][0]
+    psi = O.run(ops, n)
+    vals, energy = O.expect_terms(psi, terms)
+    want = qaoa_p1_edge_zz(gamma, beta, edges, n)
+    assert np.max(np.abs(vals - want)) <= 1e-13
+    assert abs(energy - want.sum()) <= 1e-12
