@@ -1,0 +1,284 @@
+/*
+ * sv.h -- C ABI of the MI355X (gfx950) state-vector library.
+ *
+ * The library keeps one or more 2^n-amplitude state vectors resident in HBM
+ * and runs a circuit, given as a list of gates, against them (the paper's
+ * framing of a circuit as a gate list executed by a backend, Sec. III-A). The
+ * state-vector method itself is Sec. II: the whole state is stored and every
+ * gate updates it. Sampling and expectation values follow Sec. III-B: the
+ * circuit is simulated once, then every shot is drawn from the final state and
+ * expectation values are evaluated on that cached state.
+ *
+ * Conventions
+ *  - Qubit q is bit q of the amplitude index (little-endian, as in the
+ *    Qiskit/OpenQASM2 circuits the paper takes as input, Sec. III-A).
+ *  - A k-qubit matrix U is row-major, 2^k x 2^k complex128, stored as
+ *    interleaved (re, im) doubles; bit j of its row/column index belongs to
+ *    targets[j]. A gate with controls acts as U on the subspace where every
+ *    control qubit is 1 and as the identity elsewhere.
+ *  - States are interleaved complex arrays in device memory: complex64
+ *    (float re, im; 8 bytes per amplitude) or complex128 (16 bytes).
+ *  - Every function returns an sv_status; SV_OK is 0, errors are negative.
+ *    On error, sv_last_error() returns a message for the calling thread.
+ *    No C++ exception crosses this interface.
+ *  - Ownership: every input array is owned by the caller and is read (or
+ *    copied) before the call returns; every output array is owned by the
+ *    caller. State memory lives in the context's arena.
+ *  - Ordering: gate calls are asynchronous and ordered on the state's HIP
+ *    stream. Calls that return host results (sv_sample, sv_expect, sv_norm,
+ *    sv_copy_out) wait for that stream. One host thread at a time may use a
+ *    given state; an sv_server is safe to use from several threads.
+ */
+#ifndef SV_H
+#define SV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SV_OK = 0,
+    SV_PENDING = 1,         /* sv_poll: the request has not finished yet */
+    SV_E_INVALID = -1,      /* bad argument: n, qubit index, duplicate qubit, k, size, null pointer */
+    SV_E_OOM = -2,          /* the arena cannot hold the requested memory */
+    SV_E_DEVICE = -3,       /* a HIP runtime call failed */
+    SV_E_NUMERIC = -4,      /* non-finite matrix entry, or a zero-norm state */
+    SV_E_NOTFOUND = -5,     /* unknown request id */
+    SV_E_BUSY = -6,         /* the server queue is full */
+    SV_E_UNSUPPORTED = -7   /* valid request outside what this build implements */
+} sv_status;
+
+typedef enum { SV_C64 = 0, SV_C128 = 1 } sv_dtype;
+
+typedef struct sv_ctx_s *sv_ctx;
+typedef struct sv_state_s *sv_state;
+typedef struct sv_server_s *sv_server;
+
+/* Largest supported widths: 2^34 complex64 or 2^33 complex128 amplitudes
+ * (128 GiB) fit one 288 GB device. */
+#define SV_MAX_QUBITS_C64 34
+#define SV_MAX_QUBITS_C128 33
+/* Largest dense block for sv_apply_fused and for fusion in sv_run. */
+#define SV_MAX_FUSED 5
+
+/* ------------------------------------------------------------ context */
+
+typedef struct {
+    int device;            /* HIP device ordinal the context works on */
+    void *arena;           /* device memory block the context sub-allocates states and
+                              workspaces from, owned by the caller (e.g. a torch tensor)
+                              and kept alive until sv_ctx_destroy; NULL: the library
+                              allocates arena_bytes itself and frees them on destroy */
+    uint64_t arena_bytes;  /* size of that block in bytes (> 0) */
+    void *stream;          /* hipStream_t for new states; NULL: the library creates one
+                              at the default priority */
+    int renorm_period;     /* complex64 states: sv_run rescales the state to unit norm
+                              every this many gates and at the end (0: never) */
+} sv_ctx_opts;
+
+/* Create a context. opts must not be NULL. */
+sv_status sv_ctx_create(const sv_ctx_opts *opts, sv_ctx *out);
+/* Destroy a context; every state and server made from it must be destroyed first. */
+sv_status sv_ctx_destroy(sv_ctx ctx);
+/* Bytes of the arena still free (largest free extent in *largest, may be NULL). */
+sv_status sv_ctx_free_bytes(sv_ctx ctx, uint64_t *total_free, uint64_t *largest);
+
+/* ------------------------------------------------------------- states */
+
+/* Allocate a state of n qubits (1 <= n <= SV_MAX_QUBITS_*) set to |0...0>
+ * (Sec. II: the full 2^n amplitude vector). SV_E_OOM if the arena lacks
+ * 2^n * (8 or 16) bytes plus a small measurement workspace. */
+sv_status sv_create(sv_ctx ctx, int n, sv_dtype dtype, sv_state *out);
+sv_status sv_destroy(sv_state st);
+/* psi <- |basis>, basis < 2^n. */
+sv_status sv_reset(sv_state st, uint64_t basis);
+/* Put the state's work on another HIP stream (NULL: the context's stream). */
+sv_status sv_set_stream(sv_state st, void *stream);
+/* Wait for every call queued on the state's stream. */
+sv_status sv_synchronize(sv_state st);
+/* Device address of the amplitudes and their byte size (read-only use by the caller). */
+sv_status sv_device_ptr(sv_state st, void **ptr, uint64_t *bytes);
+/* Copy the amplitudes to / from host memory; bytes must equal the state's size. */
+sv_status sv_copy_out(sv_state st, void *host_dst, uint64_t bytes);
+sv_status sv_copy_in(sv_state st, const void *host_src, uint64_t bytes);
+
+/* --------------------------------------------------------------- gates */
+
+/* Apply a k-qubit matrix (1 <= k <= 2) to `targets` on the subspace where all
+ * `controls` are 1 (Sec. II's gate update; ncontrols may be 0, controls may then
+ * be NULL). Targets and controls must be distinct and < n. The matrix is
+ * classified on the host (diagonal, single-phase, two-level, dense) and only the
+ * amplitudes it changes are read and written. U must be finite; unitarity is not
+ * checked. */
+sv_status sv_apply_gate(sv_state st, const double *U, int k, const int *targets,
+                        const int *controls, int ncontrols);
+
+/* Apply a dense k-qubit block (1 <= k <= SV_MAX_FUSED) to `targets`: every
+ * group of 2^k amplitudes that differ only in the target bits is multiplied by
+ * U as one 2^k x 2^k complex matrix product. */
+sv_status sv_apply_fused(sv_state st, const double *U, int k, const int *targets);
+
+/* Gate kinds of sv_op. Names and matrices are Qiskit's (Sec. III-A input
+ * format), global phase included; angles in radians. q[] lists controls first:
+ * CX/CY/CZ/CP: (control, target); CCX: (control, control, target). */
+typedef enum {
+    SV_GATE_H = 0, SV_GATE_X, SV_GATE_Y, SV_GATE_Z, SV_GATE_S, SV_GATE_SDG,
+    SV_GATE_T, SV_GATE_TDG, SV_GATE_SX, SV_GATE_RX, SV_GATE_RY, SV_GATE_RZ,
+    SV_GATE_P, SV_GATE_U3, SV_GATE_CX, SV_GATE_CY, SV_GATE_CZ, SV_GATE_CP,
+    SV_GATE_SWAP, SV_GATE_RZZ, SV_GATE_CCX, SV_GATE_COUNT
+} sv_gate_kind;
+
+#define SV_OP_ADJOINT 1   /* sv_op.flags: apply the conjugate transpose */
+
+typedef struct {
+    int32_t kind;     /* sv_gate_kind */
+    int32_t flags;    /* SV_OP_ADJOINT or 0 */
+    int32_t q[3];     /* qubits, controls first */
+    int32_t pad;
+    double p[3];      /* angles: RX RY RZ P CP RZZ use p[0]; U3 uses theta, phi, lambda */
+} sv_op;
+
+/* The 2^k x 2^k matrix of a gate kind on its target qubits and its number of
+ * controls (host only, no state needed). U_out holds 16 complex128 values. */
+sv_status sv_gate_matrix(int kind, const double *params, int adjoint, double *U_out,
+                         int *k_out, int *ncontrols_out);
+
+/* Run a gate list in order. fuse_k = 0 launches one kernel per gate; 2..5 first
+ * groups consecutive gates greedily into blocks of at most fuse_k qubits
+ * (block matrix = product of the embedded gate matrices, formed in complex128
+ * on the host) and applies each block with sv_apply_fused's kernels. Gates that
+ * only change a phase on a subspace are never fused. */
+sv_status sv_run(sv_state st, const sv_op *ops, int nops, int fuse_k);
+
+/* Fusion plan of a gate list without running it: number of blocks and of ops
+ * left unfused. */
+sv_status sv_plan_fusion(const sv_op *ops, int nops, int n, int fuse_k, int *nblocks,
+                         int *nsingle);
+
+/* --------------------------------------------------------- measurement */
+
+/* Squared norm sum |psi_i|^2, accumulated in FP64 with compensated (TwoSum /
+ * Neumaier) combination in a fixed order that depends only on n. */
+sv_status sv_norm(sv_state st, double *out);
+/* psi <- psi / ||psi|| on the device (no host round trip). */
+sv_status sv_renormalize(sv_state st);
+
+/* Terminal measurement of every qubit, `shots` times (Sec. III-B: simulate once,
+ * then draw every shot from the final state). Shot s draws
+ * u_s = (SplitMix64_s(seed) >> 11) * 2^-53, the s-th output (s from 0) of the
+ * SplitMix64 generator seeded with `seed`, and returns the smallest index i
+ * whose FP64 cumulative probability F(i) = sum_{j<=i} |psi_j|^2 exceeds
+ * u_s * F(2^n - 1). out (caller-owned, `shots` entries) receives the indices in
+ * shot order. shots may be 0. */
+sv_status sv_sample(sv_state st, int64_t shots, uint64_t seed, uint64_t *out);
+
+/* One Pauli string P = i^{popcount(x & z)} X^x Z^z (bit q of xmask/zmask: X or Z
+ * on qubit q; both set: Y), with a real coefficient. */
+typedef struct {
+    uint64_t xmask;
+    uint64_t zmask;
+    double coeff;
+} sv_pauli;
+
+/* Expectation values <psi|P_t|psi> / <psi|psi> on the resident state
+ * (Sec. III-B), accumulated in FP64 with compensated combination. out_each
+ * (caller-owned, nterms entries, may be NULL) receives each real part;
+ * out_weighted (may be NULL) receives sum_t coeff_t <P_t>. Terms without X/Y
+ * share one pass over the state; each other term takes one pass. */
+sv_status sv_expect(sv_state st, const sv_pauli *terms, int nterms, double *out_each,
+                    double *out_weighted);
+
+/* ----------------------------------------------------------- profiling */
+
+/* When enabled, every kernel the library launches is bracketed by HIP events
+ * on its stream, and sv_trace_read returns, per kernel class, the launch count,
+ * the summed event time and the summed algorithmic bytes (the bytes the method
+ * must move: reads plus writes of the amplitudes a gate changes). */
+typedef struct {
+    char name[32];
+    uint64_t launches;
+    double seconds;
+    double bytes;
+} sv_trace_rec;
+
+sv_status sv_trace_enable(sv_ctx ctx, int on);
+/* Waits for outstanding traced work, fills up to cap records, sets *count to the
+ * number of classes seen, and clears the counters. */
+sv_status sv_trace_read(sv_ctx ctx, sv_trace_rec *out, int cap, int *count);
+
+/* ------------------------------------------------------------- serving */
+
+typedef struct {
+    uint64_t arena_bytes;   /* 0: the whole context arena may hold request states */
+    int max_active;         /* most requests resident at once (0: 256) */
+    int small_qubits;       /* requests with n <= this run in the packed persistent
+                               kernel (0: 13 for complex64, 12 for complex128) */
+    int max_queue;          /* most queued requests before sv_submit returns SV_E_BUSY (0: 1<<20) */
+    int nstreams;           /* HIP streams the driver spreads large requests over (0: 4) */
+} sv_server_opts;
+
+typedef struct {
+    int32_t n;              /* qubits */
+    int32_t dtype;          /* sv_dtype */
+    const sv_op *ops;       /* gate list (deep-copied by sv_submit) */
+    int32_t nops;
+    int32_t fuse_k;         /* as in sv_run */
+    int64_t shots;          /* terminal measurement shots (0: none) */
+    uint64_t seed;          /* sampling seed */
+    const sv_pauli *terms;  /* expectation terms (deep-copied; may be NULL) */
+    int32_t nterms;
+    int32_t pad;
+} sv_circuit;
+
+typedef struct {
+    uint64_t *samples;      /* caller buffer of >= shots entries, or NULL */
+    double *expect;         /* caller buffer of >= nterms entries, or NULL */
+    double weighted;        /* sum coeff_t <P_t> */
+    double norm;            /* squared norm of the final state before measurement */
+    int32_t status;         /* the request's own sv_status */
+    int32_t pad;
+    uint64_t t_submit_ns;   /* steady-clock timestamps (ns) */
+    uint64_t t_admit_ns;
+    uint64_t t_done_ns;
+} sv_result;
+
+/* Start a server: one driver thread (the paper runs GPU backends from a single
+ * host thread, Sec. III-B) that admits queued circuits while their 2^n state
+ * fits the arena and a slot is free, keeps admitted states resident, packs
+ * small circuits into one persistent kernel launch, and interleaves the gates of
+ * larger ones across streams so that their work overlaps on the device. */
+sv_status sv_server_create(sv_ctx ctx, const sv_server_opts *opts, sv_server *out);
+/* Stop the driver after the work in flight and free everything. */
+sv_status sv_server_destroy(sv_server srv);
+/* Queue a circuit; *req_id identifies it. The circuit is validated and deep-copied. */
+sv_status sv_submit(sv_server srv, const sv_circuit *c, uint64_t *req_id);
+/* Non-blocking: SV_PENDING while queued or running; SV_OK once finished, after
+ * copying samples / expectations into the caller's buffers in *out and releasing
+ * the request (a second poll returns SV_E_NOTFOUND). A failed request returns SV_OK
+ * with out->status < 0. */
+sv_status sv_poll(sv_server srv, uint64_t req_id, sv_result *out);
+/* Blocking poll with a timeout in milliseconds (< 0: no timeout). */
+sv_status sv_wait(sv_server srv, uint64_t req_id, sv_result *out, int64_t timeout_ms);
+/* Remove a request that has not been admitted yet; SV_E_BUSY once it runs. */
+sv_status sv_cancel(sv_server srv, uint64_t req_id);
+
+typedef struct {
+    uint64_t submitted, admitted, completed, rejected, cancelled;
+    uint64_t packed_launches, packed_circuits;
+    uint64_t queued, active;
+    uint64_t peak_bytes;
+} sv_server_stats;
+sv_status sv_server_stats_get(sv_server srv, sv_server_stats *out);
+
+/* Message of the calling thread's last error (never NULL). */
+const char *sv_last_error(void);
+/* Library version string. */
+const char *sv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SV_H */

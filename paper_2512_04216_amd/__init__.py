@@ -1,0 +1,247 @@
+"""MI355X (gfx950) state-vector simulator: Python binding of libsvsim.so.
+
+Every step of the simulation runs in the library's HIP kernels; this module
+only marshals arguments. PyTorch provides the device memory arena (one
+uint8 tensor) and the HIP stream the library works on.
+
+The functions ``sv_*`` mirror the C ABI of include/sv.h one to one; the
+classes ``Context``, ``State`` and ``Server`` are conveniences over them.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _abi
+from ._abi import (  # noqa: F401
+    GATE_KIND, GATE_KINDS, SV_C64, SV_C128, SV_OP_ADJOINT, SvError, check, load, sv_op, sv_pauli,
+)
+
+__all__ = ["Context", "State", "Server", "ops_to_array", "terms_to_array", "SvError", "load",
+           "GATE_KIND", "SV_C64", "SV_C128"]
+
+
+def lib():
+    return load()
+
+
+def _dtype_code(dtype) -> int:
+    if dtype in (SV_C64, "c64", "complex64", np.complex64):
+        return SV_C64
+    if dtype in (SV_C128, "c128", "complex128", np.complex128):
+        return SV_C128
+    raise ValueError("dtype must be complex64 or complex128")
+
+
+def ops_to_array(ops):
+    """Gate list [(name, qubits, params)] or [(name, qubits, params, adjoint)] -> sv_op array."""
+    arr = (sv_op * max(1, len(ops)))()
+    for i, op in enumerate(ops):
+        name, qubits, params = op[0], op[1], op[2]
+        adj = bool(op[3]) if len(op) > 3 else False
+        o = arr[i]
+        o.kind = GATE_KIND[name]
+        o.flags = SV_OP_ADJOINT if adj else 0
+        for j, q in enumerate(qubits):
+            o.q[j] = int(q)
+        for j, p in enumerate(params):
+            o.p[j] = float(p)
+    return arr
+
+
+def inverse_ops(ops):
+    """The inverse circuit: reversed order, every gate flagged adjoint."""
+    return [(op[0], op[1], op[2], not (len(op) > 3 and op[3])) for op in reversed(ops)]
+
+
+def terms_to_array(terms):
+    arr = (sv_pauli * max(1, len(terms)))()
+    for i, (x, z, c) in enumerate(terms):
+        arr[i].xmask, arr[i].zmask, arr[i].coeff = int(x), int(z), float(c)
+    return arr
+
+
+def _cmatrix(U):
+    U = np.ascontiguousarray(np.asarray(U, dtype=np.complex128))
+    return U, U.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ints(xs):
+    a = (ctypes.c_int * max(1, len(xs)))(*[int(x) for x in xs])
+    return a
+
+
+# ---------------------------------------------------------------- raw ABI mirror
+def sv_gate_matrix(kind, params=(), adjoint=False):
+    U = np.zeros(16, dtype=np.complex128)
+    p = (ctypes.c_double * 3)(*(list(params) + [0.0] * (3 - len(params))))
+    k, nc = ctypes.c_int(), ctypes.c_int()
+    kind = GATE_KIND[kind] if isinstance(kind, str) else int(kind)
+    check(lib().sv_gate_matrix(kind, p, int(adjoint), U.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               ctypes.byref(k), ctypes.byref(nc)))
+    K = 1 << k.value
+    return U[: K * K].reshape(K, K).copy(), k.value, nc.value
+
+
+def sv_plan_fusion(ops, n, fuse_k):
+    arr = ops_to_array(ops)
+    nb, ns = ctypes.c_int(), ctypes.c_int()
+    check(lib().sv_plan_fusion(arr, len(ops), n, fuse_k, ctypes.byref(nb), ctypes.byref(ns)))
+    return nb.value, ns.value
+
+
+class Context:
+    """A device context: an HBM arena (a torch uint8 tensor unless
+    `use_torch=False`) and the HIP stream new states use."""
+
+    def __init__(self, arena_bytes: int | None = None, device: int = 0, renorm_period: int = 64,
+                 use_torch: bool = True, stream=None):
+        L = lib()
+        self._tensor = None
+        arena_ptr = None
+        stream_ptr = None
+        if use_torch:
+            import torch
+
+            torch.cuda.set_device(device)
+            if arena_bytes is None:
+                free, _total = torch.cuda.mem_get_info(device)
+                arena_bytes = int(free * 0.9) & ~((1 << 21) - 1)
+            self._tensor = torch.empty(int(arena_bytes), dtype=torch.uint8, device="cuda:%d" % device)
+            arena_ptr = self._tensor.data_ptr()
+            if stream is None:
+                stream = torch.cuda.current_stream(device)
+            self._torch_stream = stream
+            stream_ptr = stream.cuda_stream
+        elif arena_bytes is None:
+            raise ValueError("arena_bytes is required without torch")
+        opts = _abi.sv_ctx_opts(device=device, arena=arena_ptr, arena_bytes=int(arena_bytes),
+                                stream=stream_ptr, renorm_period=int(renorm_period))
+        h = ctypes.c_void_p()
+        check(L.sv_ctx_create(ctypes.byref(opts), ctypes.byref(h)))
+        self.handle = h
+        self.arena_bytes = int(arena_bytes)
+
+    def free_bytes(self):
+        t, l = ctypes.c_uint64(), ctypes.c_uint64()
+        check(lib().sv_ctx_free_bytes(self.handle, ctypes.byref(t), ctypes.byref(l)))
+        return t.value, l.value
+
+    def trace(self, on: bool = True):
+        check(lib().sv_trace_enable(self.handle, int(on)))
+
+    def trace_read(self):
+        recs = (_abi.sv_trace_rec * 64)()
+        cnt = ctypes.c_int()
+        check(lib().sv_trace_read(self.handle, recs, 64, ctypes.byref(cnt)))
+        return {recs[i].name.decode(): {"launches": recs[i].launches, "seconds": recs[i].seconds,
+                                        "bytes": recs[i].bytes} for i in range(min(cnt.value, 64))}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            check(lib().sv_ctx_destroy(self.handle))
+            self.handle = None
+            self._tensor = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class State:
+    """A resident state vector of n qubits (complex64 or complex128)."""
+
+    def __init__(self, ctx: Context, n: int, dtype="c128"):
+        self.ctx = ctx
+        self.n = int(n)
+        self.dtype = _dtype_code(dtype)
+        h = ctypes.c_void_p()
+        check(lib().sv_create(ctx.handle, self.n, self.dtype, ctypes.byref(h)))
+        self.handle = h
+
+    @property
+    def np_dtype(self):
+        return np.complex64 if self.dtype == SV_C64 else np.complex128
+
+    def close(self):
+        if getattr(self, "handle", None):
+            check(lib().sv_destroy(self.handle))
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def reset(self, basis: int = 0):
+        check(lib().sv_reset(self.handle, int(basis)))
+        return self
+
+    def synchronize(self):
+        check(lib().sv_synchronize(self.handle))
+
+    def set_stream(self, stream_ptr):
+        check(lib().sv_set_stream(self.handle, stream_ptr))
+
+    def device_ptr(self):
+        p, b = ctypes.c_void_p(), ctypes.c_uint64()
+        check(lib().sv_device_ptr(self.handle, ctypes.byref(p), ctypes.byref(b)))
+        return p.value, b.value
+
+    def apply_gate(self, U, targets, controls=()):
+        U, Up = _cmatrix(U)
+        check(lib().sv_apply_gate(self.handle, Up, len(targets), _ints(targets), _ints(controls), len(controls)))
+        return self
+
+    def apply_fused(self, U, targets):
+        U, Up = _cmatrix(U)
+        check(lib().sv_apply_fused(self.handle, Up, len(targets), _ints(targets)))
+        return self
+
+    def run(self, ops, fuse_k: int = 0):
+        arr = ops_to_array(ops)
+        check(lib().sv_run(self.handle, arr, len(ops), int(fuse_k)))
+        return self
+
+    def norm2(self) -> float:
+        v = ctypes.c_double()
+        check(lib().sv_norm(self.handle, ctypes.byref(v)))
+        return v.value
+
+    def renormalize(self):
+        check(lib().sv_renormalize(self.handle))
+        return self
+
+    def sample(self, shots: int, seed: int) -> np.ndarray:
+        out = np.zeros(max(1, shots), dtype=np.uint64)
+        check(lib().sv_sample(self.handle, int(shots), int(seed) & (2**64 - 1),
+                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
+        return out[:shots]
+
+    def expect(self, terms):
+        """terms: [(xmask, zmask, coeff)] -> (values, weighted sum)."""
+        arr = terms_to_array(terms)
+        vals = np.zeros(max(1, len(terms)), dtype=np.float64)
+        w = ctypes.c_double()
+        check(lib().sv_expect(self.handle, arr, len(terms), vals.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              ctypes.byref(w)))
+        return vals[: len(terms)], w.value
+
+    def copy_out(self) -> np.ndarray:
+        out = np.empty(1 << self.n, dtype=self.np_dtype)
+        check(lib().sv_copy_out(self.handle, out.ctypes.data, out.nbytes))
+        return out
+
+    def copy_in(self, psi):
+        psi = np.ascontiguousarray(np.asarray(psi, dtype=self.np_dtype))
+        if psi.size != (1 << self.n):
+            raise ValueError("state size mismatch")
+        check(lib().sv_copy_in(self.handle, psi.ctypes.data, psi.nbytes))
+        return self
+
+
+from .serving import Server  # noqa: E402,F401

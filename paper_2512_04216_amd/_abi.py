@@ -1,0 +1,147 @@
+"""ctypes declarations of the C ABI in include/sv.h (argument marshalling only).
+
+The shared library is loaded from this package directory. If it is missing
+the import fails loudly: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsvsim.so")
+
+SV_OK, SV_PENDING = 0, 1
+SV_E_INVALID, SV_E_OOM, SV_E_DEVICE, SV_E_NUMERIC = -1, -2, -3, -4
+SV_E_NOTFOUND, SV_E_BUSY, SV_E_UNSUPPORTED = -5, -6, -7
+SV_C64, SV_C128 = 0, 1
+SV_OP_ADJOINT = 1
+SV_MAX_QUBITS_C64, SV_MAX_QUBITS_C128, SV_MAX_FUSED = 34, 33, 5
+
+STATUS_NAMES = {0: "SV_OK", 1: "SV_PENDING", -1: "SV_E_INVALID", -2: "SV_E_OOM", -3: "SV_E_DEVICE",
+                -4: "SV_E_NUMERIC", -5: "SV_E_NOTFOUND", -6: "SV_E_BUSY", -7: "SV_E_UNSUPPORTED"}
+
+# sv_gate_kind, in declaration order
+GATE_KINDS = ["h", "x", "y", "z", "s", "sdg", "t", "tdg", "sx", "rx", "ry", "rz", "p", "u3",
+              "cx", "cy", "cz", "cp", "swap", "rzz", "ccx"]
+GATE_KIND = {name: i for i, name in enumerate(GATE_KINDS)}
+
+
+class sv_ctx_opts(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_uint64),
+                ("stream", ctypes.c_void_p), ("renorm_period", ctypes.c_int)]
+
+
+class sv_op(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("flags", ctypes.c_int32), ("q", ctypes.c_int32 * 3),
+                ("pad", ctypes.c_int32), ("p", ctypes.c_double * 3)]
+
+
+class sv_pauli(ctypes.Structure):
+    _fields_ = [("xmask", ctypes.c_uint64), ("zmask", ctypes.c_uint64), ("coeff", ctypes.c_double)]
+
+
+class sv_trace_rec(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_uint64), ("seconds", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
+
+
+class sv_server_opts(ctypes.Structure):
+    _fields_ = [("arena_bytes", ctypes.c_uint64), ("max_active", ctypes.c_int), ("small_qubits", ctypes.c_int),
+                ("max_queue", ctypes.c_int), ("nstreams", ctypes.c_int)]
+
+
+class sv_circuit(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("dtype", ctypes.c_int32), ("ops", ctypes.POINTER(sv_op)),
+                ("nops", ctypes.c_int32), ("fuse_k", ctypes.c_int32), ("shots", ctypes.c_int64),
+                ("seed", ctypes.c_uint64), ("terms", ctypes.POINTER(sv_pauli)), ("nterms", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
+
+
+class sv_result(ctypes.Structure):
+    _fields_ = [("samples", ctypes.POINTER(ctypes.c_uint64)), ("expect", ctypes.POINTER(ctypes.c_double)),
+                ("weighted", ctypes.c_double), ("norm", ctypes.c_double), ("status", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("t_submit_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64),
+                ("t_done_ns", ctypes.c_uint64)]
+
+
+class sv_server_stats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint64) for f in ("submitted", "admitted", "completed", "rejected", "cancelled",
+                                               "packed_launches", "packed_circuits", "queued", "active",
+                                               "peak_bytes")]
+
+
+P = ctypes.c_void_p
+I32 = ctypes.c_int
+U64 = ctypes.c_uint64
+I64 = ctypes.c_int64
+DP = ctypes.POINTER(ctypes.c_double)
+IP = ctypes.POINTER(ctypes.c_int)
+U64P = ctypes.POINTER(ctypes.c_uint64)
+
+# name -> (argtypes); every function returns sv_status (int) unless listed in _RESTYPE
+PROTOTYPES = {
+    "sv_ctx_create": [ctypes.POINTER(sv_ctx_opts), ctypes.POINTER(P)],
+    "sv_ctx_destroy": [P],
+    "sv_ctx_free_bytes": [P, U64P, U64P],
+    "sv_create": [P, I32, I32, ctypes.POINTER(P)],
+    "sv_destroy": [P],
+    "sv_reset": [P, U64],
+    "sv_set_stream": [P, P],
+    "sv_synchronize": [P],
+    "sv_device_ptr": [P, ctypes.POINTER(P), U64P],
+    "sv_copy_out": [P, P, U64],
+    "sv_copy_in": [P, P, U64],
+    "sv_apply_gate": [P, DP, I32, IP, IP, I32],
+    "sv_apply_fused": [P, DP, I32, IP],
+    "sv_gate_matrix": [I32, DP, I32, DP, IP, IP],
+    "sv_run": [P, ctypes.POINTER(sv_op), I32, I32],
+    "sv_plan_fusion": [ctypes.POINTER(sv_op), I32, I32, I32, IP, IP],
+    "sv_norm": [P, DP],
+    "sv_renormalize": [P],
+    "sv_sample": [P, I64, U64, U64P],
+    "sv_expect": [P, ctypes.POINTER(sv_pauli), I32, DP, DP],
+    "sv_trace_enable": [P, I32],
+    "sv_trace_read": [P, ctypes.POINTER(sv_trace_rec), I32, IP],
+    "sv_server_create": [P, ctypes.POINTER(sv_server_opts), ctypes.POINTER(P)],
+    "sv_server_destroy": [P],
+    "sv_submit": [P, ctypes.POINTER(sv_circuit), U64P],
+    "sv_poll": [P, U64, ctypes.POINTER(sv_result)],
+    "sv_wait": [P, U64, ctypes.POINTER(sv_result), I64],
+    "sv_cancel": [P, U64],
+    "sv_server_stats_get": [P, ctypes.POINTER(sv_server_stats)],
+    "sv_last_error": [],
+    "sv_version": [],
+}
+_RESTYPE = {"sv_last_error": ctypes.c_char_p, "sv_version": ctypes.c_char_p}
+
+_lib = None
+
+
+class SvError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+def load(path: str = LIB_PATH):
+    """Load libsvsim.so and declare every prototype. Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libsvsim.so is not built (%s); run paper_2512_04216_amd.build.build()" % path)
+    L = ctypes.CDLL(path)
+    for name, args in PROTOTYPES.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = _RESTYPE.get(name, ctypes.c_int)
+    _lib = L
+    return L
+
+
+def check(status: int, allow=(SV_OK,)):
+    if status in allow:
+        return status
+    msg = _lib.sv_last_error().decode() if _lib is not None else ""
+    raise SvError(status, msg)

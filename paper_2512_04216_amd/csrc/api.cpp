@@ -1,0 +1,647 @@
+// api.cpp -- the C ABI of the state-vector library (contexts, states, gates,
+// gate lists, measurement, tracing). Declared in include/sv.h.
+#include "sv_host.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
+namespace svh {
+
+static thread_local std::string g_err = "no error";
+
+sv_status fail(sv_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+sv_status hip_fail(hipError_t e, const char *what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return SV_E_DEVICE;
+}
+
+// ---- arena --------------------------------------------------------------------
+void Arena::init(char *base, uint64_t size) {
+    std::lock_guard<std::mutex> g(mu_);
+    base_ = base;
+    size_ = size;
+    free_.clear();
+    used_.clear();
+    if (size) free_[0] = size;
+}
+
+void *Arena::alloc(uint64_t bytes, uint64_t align) {
+    std::lock_guard<std::mutex> g(mu_);
+    if (bytes == 0) bytes = 1;
+    bytes = (bytes + 255) & ~255ull;
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+        const uint64_t off = it->first, len = it->second;
+        const uint64_t a = (off + align - 1) / align * align;
+        if (a + bytes > off + len) continue;
+        free_.erase(it);
+        if (a > off) free_[off] = a - off;
+        if (a + bytes < off + len) free_[a + bytes] = off + len - (a + bytes);
+        used_[a] = bytes;
+        return base_ + a;
+    }
+    return nullptr;
+}
+
+void Arena::free(void *p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> g(mu_);
+    const uint64_t off = (uint64_t)((char *)p - base_);
+    auto u = used_.find(off);
+    if (u == used_.end()) return;
+    uint64_t start = off, len = u->second;
+    used_.erase(u);
+    auto nx = free_.lower_bound(start);
+    if (nx != free_.end() && nx->first == start + len) {
+        len += nx->second;
+        free_.erase(nx);
+    }
+    auto pv = free_.lower_bound(start);
+    if (pv != free_.begin()) {
+        --pv;
+        if (pv->first + pv->second == start) {
+            start = pv->first;
+            len += pv->second;
+            free_.erase(pv);
+        }
+    }
+    free_[start] = len;
+}
+
+uint64_t Arena::free_bytes() const {
+    std::lock_guard<std::mutex> g(mu_);
+    uint64_t t = 0;
+    for (auto &f : free_) t += f.second;
+    return t;
+}
+
+uint64_t Arena::largest_free() const {
+    std::lock_guard<std::mutex> g(mu_);
+    uint64_t t = 0;
+    for (auto &f : free_) t = std::max(t, f.second);
+    return t;
+}
+
+bool Arena::contains(const void *p) const { return (const char *)p >= base_ && (const char *)p < base_ + size_; }
+
+// ---- tracing ------------------------------------------------------------------
+hipEvent_t Tracer::get_event() {
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+TraceScope::TraceScope(Tracer *tr, hipStream_t st, const char *nm, double by) : t(tr), s(st), name(nm), bytes(by) {
+    if (!t || !t->on) return;
+    std::lock_guard<std::mutex> g(t->mu);
+    a = t->get_event();
+    b = t->get_event();
+    if (a) hipEventRecord(a, s);
+}
+
+TraceScope::~TraceScope() {
+    if (!a || !b) return;
+    hipEventRecord(b, s);
+    std::lock_guard<std::mutex> g(t->mu);
+    t->pending.push_back(Tracer::Pending{name, a, b, bytes});
+}
+
+// ---- parameter ring -----------------------------------------------------------
+sv_status ParamRing::init(int slots, uint64_t bytes) {
+    nslots = slots;
+    slot_bytes = (bytes + 255) & ~255ull;
+    SV_HIP(hipHostMalloc((void **)&host, nslots * slot_bytes, hipHostMallocDefault));
+    ev.assign(nslots, nullptr);
+    used.assign(nslots, false);
+    for (int i = 0; i < nslots; ++i) SV_HIP(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+    return SV_OK;
+}
+
+void ParamRing::destroy() {
+    for (auto e : ev)
+        if (e) hipEventDestroy(e);
+    ev.clear();
+    if (host) hipHostFree(host);
+    host = nullptr;
+}
+
+int ParamRing::acquire() {
+    std::lock_guard<std::mutex> g(mu);
+    const int s = next;
+    next = (next + 1) % nslots;
+    if (used[s]) hipEventSynchronize(ev[s]);
+    used[s] = true;
+    return s;
+}
+
+void ParamRing::release_after(int slot, hipStream_t s) { hipEventRecord(ev[slot], s); }
+
+uint64_t state_bytes(int n, sv_dtype dt) {
+    const uint64_t b = (1ull << n) * (dt == SV_C64 ? 8ull : 16ull);
+    return std::max<uint64_t>(b, 16);
+}
+
+sv_status apply_fused(sv_state st, const cd *U, int k, const int *targets) {
+    static const bool no_mfma = std::getenv("SV_NO_MFMA") != nullptr;
+    sv_ctx c = st->ctx;
+    const int slot = c->ring.acquire();
+    void *hostp = c->ring.host + (uint64_t)slot * c->ring.slot_bytes;
+    void *devp = c->ring.dev + (uint64_t)slot * c->ring.slot_bytes;
+    const int s = st->is_c64() ? 8 : 16;
+    const bool mfma = !no_mfma && st->n >= 4 + std::max(k, 4);
+    hipError_t e;
+    {
+        TraceScope ts(&c->tracer, st->stream, mfma ? "fused_mfma" : "fused_generic", 2.0 * s * std::ldexp(1.0, st->n));
+        e = svk::launch_fused_staged(reinterpret_cast<const double *>(U), k, targets, st->psi, st->n, st->is_c64(),
+                                     st->stream, mfma ? 1 : 0, devp, hostp);
+    }
+    c->ring.release_after(slot, st->stream);
+    if (e != hipSuccess) return hip_fail(e, "fused block launch");
+    return SV_OK;
+}
+
+sv_status norm_device(sv_state st) {
+    TraceScope ts(&st->ctx->tracer, st->stream, "norm", (double)st->bytes);
+    SV_HIP(svk::launch_norm(st->psi, st->n, st->is_c64(), st->ws, st->stream));
+    return SV_OK;
+}
+
+static sv_status renorm(sv_state st) {
+    sv_status r = norm_device(st);
+    if (r) return r;
+    TraceScope ts(&st->ctx->tracer, st->stream, "scale", 2.0 * st->bytes);
+    SV_HIP(svk::launch_scale_by_norm(st->psi, st->n, st->is_c64(), svk::norm2_dev_ptr(st->ws, st->n), st->stream));
+    st->gates_since_renorm = 0;
+    return SV_OK;
+}
+
+static bool finite_all(const double *U, int count) {
+    for (int i = 0; i < count; ++i)
+        if (!std::isfinite(U[i])) return false;
+    return true;
+}
+
+static sv_status check_qubits(sv_state st, const int *q, int cnt, uint64_t *mask) {
+    uint64_t m = *mask;
+    for (int j = 0; j < cnt; ++j) {
+        if (q[j] < 0 || q[j] >= st->n) return fail(SV_E_INVALID, "qubit index out of range");
+        if ((m >> q[j]) & 1) return fail(SV_E_INVALID, "duplicate qubit");
+        m |= 1ull << q[j];
+    }
+    *mask = m;
+    return SV_OK;
+}
+
+static sv_status apply_op(sv_state st, const sv_op &o) {
+    cd U[16];
+    int k, nc;
+    if (!gate_matrix(o.kind, o.p, (o.flags & SV_OP_ADJOINT) != 0, U, &k, &nc))
+        return fail(SV_E_INVALID, "unknown gate kind");
+    return apply_matrix(st, U, k, o.q + nc, o.q, nc);
+}
+
+static sv_status validate_ops(sv_state st, const sv_op *ops, int nops) {
+    for (int i = 0; i < nops; ++i) {
+        const int nq = gate_nqubits(ops[i].kind);
+        if (nq < 0) return fail(SV_E_INVALID, "unknown gate kind at op " + std::to_string(i));
+        uint64_t m = 0;
+        sv_status r = check_qubits(st, ops[i].q, nq, &m);
+        if (r) return fail(r, "op " + std::to_string(i) + ": " + g_err);
+        if (!finite_all(ops[i].p, 3)) return fail(SV_E_NUMERIC, "non-finite angle at op " + std::to_string(i));
+    }
+    return SV_OK;
+}
+
+}  // namespace svh
+
+using namespace svh;
+
+extern "C" {
+
+const char *sv_last_error(void) { return g_err.c_str(); }
+const char *sv_version(void) { return "svsim-gfx950 1.0"; }
+
+sv_status sv_ctx_create(const sv_ctx_opts *o, sv_ctx *out) {
+    if (!o || !out) return fail(SV_E_INVALID, "null argument");
+    if (o->arena_bytes < (1ull << 20)) return fail(SV_E_INVALID, "arena_bytes must be at least 1 MiB");
+    SV_HIP(hipSetDevice(o->device));
+    sv_ctx c = new sv_ctx_s();
+    c->device = o->device;
+    c->renorm_period = std::max(0, o->renorm_period);
+    if (o->arena) {
+        c->arena_base = (char *)o->arena;
+        c->own_arena = false;
+    } else {
+        hipError_t e = hipMalloc((void **)&c->arena_base, o->arena_bytes);
+        if (e != hipSuccess) {
+            delete c;
+            return fail(SV_E_OOM, std::string("arena allocation failed: ") + hipGetErrorString(e));
+        }
+        c->own_arena = true;
+    }
+    c->arena.init(c->arena_base, o->arena_bytes);
+    if (o->stream) {
+        c->stream = (hipStream_t)o->stream;
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            if (c->own_arena) hipFree(c->arena_base);
+            delete c;
+            return hip_fail(e, "hipStreamCreate");
+        }
+        c->own_stream = true;
+    }
+    sv_status r = c->ring.init(64, svk::fused_args_bytes());
+    if (r == SV_OK) {
+        c->ring.dev = (char *)c->arena.alloc(c->ring.nslots * c->ring.slot_bytes);
+        if (!c->ring.dev) r = fail(SV_E_OOM, "arena too small for the parameter ring");
+    }
+    if (r != SV_OK) {
+        c->ring.destroy();
+        if (c->own_stream) hipStreamDestroy(c->stream);
+        if (c->own_arena) hipFree(c->arena_base);
+        delete c;
+        return r;
+    }
+    *out = c;
+    return SV_OK;
+}
+
+sv_status sv_ctx_destroy(sv_ctx c) {
+    if (!c) return fail(SV_E_INVALID, "null context");
+    if (c->nstates > 0) return fail(SV_E_BUSY, "context still has live states");
+    hipStreamSynchronize(c->stream);
+    {
+        std::lock_guard<std::mutex> g(c->tracer.mu);
+        for (auto &p : c->tracer.pending) {
+            hipEventDestroy(p.a);
+            hipEventDestroy(p.b);
+        }
+        for (auto e : c->tracer.pool) hipEventDestroy(e);
+    }
+    c->ring.destroy();
+    if (c->own_stream) hipStreamDestroy(c->stream);
+    if (c->own_arena) hipFree(c->arena_base);
+    delete c;
+    return SV_OK;
+}
+
+sv_status sv_ctx_free_bytes(sv_ctx c, uint64_t *total, uint64_t *largest) {
+    if (!c) return fail(SV_E_INVALID, "null context");
+    if (total) *total = c->arena.free_bytes();
+    if (largest) *largest = c->arena.largest_free();
+    return SV_OK;
+}
+
+sv_status sv_create(sv_ctx c, int n, sv_dtype dt, sv_state *out) {
+    if (!c || !out) return fail(SV_E_INVALID, "null argument");
+    if (dt != SV_C64 && dt != SV_C128) return fail(SV_E_INVALID, "dtype must be SV_C64 or SV_C128");
+    const int nmax = dt == SV_C64 ? SV_MAX_QUBITS_C64 : SV_MAX_QUBITS_C128;
+    if (n < 1 || n > nmax) return fail(SV_E_INVALID, "n out of range [1, " + std::to_string(nmax) + "]");
+    sv_state st = new sv_state_s();
+    st->ctx = c;
+    st->n = n;
+    st->dtype = dt;
+    st->bytes = state_bytes(n, dt);
+    st->ws_bytes = svk::measure_workspace_bytes(n);
+    st->psi = c->arena.alloc(st->bytes, 1 << 16);
+    if (!st->psi) {
+        delete st;
+        return fail(SV_E_OOM, "arena cannot hold a state of " + std::to_string(n) + " qubits");
+    }
+    st->ws = c->arena.alloc(st->ws_bytes);
+    if (!st->ws) {
+        c->arena.free(st->psi);
+        delete st;
+        return fail(SV_E_OOM, "arena cannot hold the measurement workspace");
+    }
+    st->stream = c->stream;
+    {
+        std::lock_guard<std::mutex> g(c->mu);
+        c->nstates++;
+    }
+    sv_status r = sv_reset(st, 0);
+    if (r != SV_OK) {
+        sv_destroy(st);
+        return r;
+    }
+    *out = st;
+    return SV_OK;
+}
+
+sv_status sv_destroy(sv_state st) {
+    if (!st) return fail(SV_E_INVALID, "null state");
+    hipStreamSynchronize(st->stream);
+    st->ctx->arena.free(st->ws);
+    st->ctx->arena.free(st->psi);
+    {
+        std::lock_guard<std::mutex> g(st->ctx->mu);
+        st->ctx->nstates--;
+    }
+    delete st;
+    return SV_OK;
+}
+
+sv_status sv_reset(sv_state st, uint64_t basis) {
+    if (!st) return fail(SV_E_INVALID, "null state");
+    if (basis >= (1ull << st->n)) return fail(SV_E_INVALID, "basis index >= 2^n");
+    TraceScope ts(&st->ctx->tracer, st->stream, "init", (double)st->bytes);
+    SV_HIP(svk::launch_init(st->psi, st->n, st->is_c64(), basis, st->stream));
+    st->gates_since_renorm = 0;
+    return SV_OK;
+}
+
+sv_status sv_set_stream(sv_state st, void *stream) {
+    if (!st) return fail(SV_E_INVALID, "null state");
+    SV_HIP(hipStreamSynchronize(st->stream));
+    st->stream = stream ? (hipStream_t)stream : st->ctx->stream;
+    return SV_OK;
+}
+
+sv_status sv_synchronize(sv_state st) {
+    if (!st) return fail(SV_E_INVALID, "null state");
+    SV_HIP(hipStreamSynchronize(st->stream));
+    return SV_OK;
+}
+
+sv_status sv_device_ptr(sv_state st, void **ptr, uint64_t *bytes) {
+    if (!st) return fail(SV_E_INVALID, "null state");
+    if (ptr) *ptr = st->psi;
+    if (bytes) *bytes = (1ull << st->n) * (st->is_c64() ? 8 : 16);
+    return SV_OK;
+}
+
+sv_status sv_copy_out(sv_state st, void *dst, uint64_t bytes) {
+    if (!st || !dst) return fail(SV_E_INVALID, "null argument");
+    const uint64_t want = (1ull << st->n) * (st->is_c64() ? 8 : 16);
+    if (bytes != want) return fail(SV_E_INVALID, "byte count must equal the state size");
+    SV_HIP(hipMemcpyAsync(dst, st->psi, bytes, hipMemcpyDeviceToHost, st->stream));
+    SV_HIP(hipStreamSynchronize(st->stream));
+    return SV_OK;
+}
+
+sv_status sv_copy_in(sv_state st, const void *src, uint64_t bytes) {
+    if (!st || !src) return fail(SV_E_INVALID, "null argument");
+    const uint64_t want = (1ull << st->n) * (st->is_c64() ? 8 : 16);
+    if (bytes != want) return fail(SV_E_INVALID, "byte count must equal the state size");
+    SV_HIP(hipMemcpyAsync(st->psi, src, bytes, hipMemcpyHostToDevice, st->stream));
+    SV_HIP(hipStreamSynchronize(st->stream));
+    return SV_OK;
+}
+
+sv_status sv_gate_matrix(int kind, const double *params, int adjoint, double *U_out, int *k_out, int *nc_out) {
+    if (!U_out || !k_out || !nc_out) return fail(SV_E_INVALID, "null argument");
+    static const double zero[3] = {0, 0, 0};
+    cd U[16];
+    if (!gate_matrix(kind, params ? params : zero, adjoint != 0, U, k_out, nc_out))
+        return fail(SV_E_INVALID, "unknown gate kind");
+    const int K = 1 << *k_out;
+    for (int i = 0; i < K * K; ++i) {
+        U_out[2 * i] = U[i].real();
+        U_out[2 * i + 1] = U[i].imag();
+    }
+    return SV_OK;
+}
+
+sv_status sv_apply_gate(sv_state st, const double *U, int k, const int *targets, const int *controls, int nc) {
+    if (!st || !U || !targets) return fail(SV_E_INVALID, "null argument");
+    if (k < 1 || k > 2) return fail(SV_E_INVALID, "sv_apply_gate takes k = 1 or 2 (sv_apply_fused for more)");
+    if (nc < 0 || (nc > 0 && !controls)) return fail(SV_E_INVALID, "bad controls");
+    uint64_t m = 0;
+    sv_status r = check_qubits(st, targets, k, &m);
+    if (r) return r;
+    r = check_qubits(st, controls, nc, &m);
+    if (r) return r;
+    const int K = 1 << k;
+    if (!finite_all(U, 2 * K * K)) return fail(SV_E_NUMERIC, "non-finite matrix entry");
+    return apply_matrix(st, reinterpret_cast<const cd *>(U), k, targets, controls, nc);
+}
+
+sv_status sv_apply_fused(sv_state st, const double *U, int k, const int *targets) {
+    if (!st || !U || !targets) return fail(SV_E_INVALID, "null argument");
+    if (k < 1 || k > SV_MAX_FUSED || k > st->n) return fail(SV_E_INVALID, "k out of range [1, min(5, n)]");
+    uint64_t m = 0;
+    sv_status r = check_qubits(st, targets, k, &m);
+    if (r) return r;
+    const int K = 1 << k;
+    if (!finite_all(U, 2 * K * K)) return fail(SV_E_NUMERIC, "non-finite matrix entry");
+    return apply_fused(st, reinterpret_cast<const cd *>(U), k, targets);
+}
+
+sv_status sv_plan_fusion(const sv_op *ops, int nops, int n, int fuse_k, int *nblocks, int *nsingle) {
+    if ((!ops && nops) || nops < 0) return fail(SV_E_INVALID, "bad op list");
+    if (fuse_k < 2 || fuse_k > SV_MAX_FUSED) return fail(SV_E_INVALID, "fuse_k out of range [2, 5]");
+    for (int i = 0; i < nops; ++i) {
+        const int nq = gate_nqubits(ops[i].kind);
+        if (nq < 0 || nq > fuse_k) return fail(SV_E_INVALID, "bad op");
+        for (int j = 0; j < nq; ++j)
+            if (ops[i].q[j] < 0 || ops[i].q[j] >= n) return fail(SV_E_INVALID, "qubit out of range");
+    }
+    auto blocks = plan_fusion(ops, nops, fuse_k);
+    int single = 0;
+    for (auto &b : blocks) single += b.ops.size() == 1;
+    if (nblocks) *nblocks = (int)blocks.size();
+    if (nsingle) *nsingle = single;
+    return SV_OK;
+}
+
+sv_status sv_run(sv_state st, const sv_op *ops, int nops, int fuse_k) {
+    if (!st || (!ops && nops) || nops < 0) return fail(SV_E_INVALID, "bad argument");
+    if (fuse_k != 0 && (fuse_k < 2 || fuse_k > SV_MAX_FUSED)) return fail(SV_E_INVALID, "fuse_k must be 0 or 2..5");
+    sv_status r = validate_ops(st, ops, nops);
+    if (r) return r;
+    const int R = st->is_c64() ? st->ctx->renorm_period : 0;
+    auto after = [&](int gates) -> sv_status {
+        if (R <= 0) return SV_OK;
+        st->gates_since_renorm += gates;
+        if (st->gates_since_renorm >= R) return renorm(st);
+        return SV_OK;
+    };
+    if (fuse_k == 0 || std::min(fuse_k, st->n) < 2) {
+        for (int i = 0; i < nops; ++i) {
+            r = apply_op(st, ops[i]);
+            if (r) return r;
+            r = after(1);
+            if (r) return r;
+        }
+    } else {
+        const int kmax = std::min(fuse_k, st->n);
+        auto blocks = plan_fusion(ops, nops, kmax);
+        std::vector<cd> U;
+        for (auto &b : blocks) {
+            if (b.ops.size() == 1) {
+                r = apply_op(st, ops[b.ops[0]]);
+            } else {
+                block_matrix(ops, b, U);
+                const int k = (int)b.qubits.size();
+                if (k <= 2) r = apply_matrix(st, U.data(), k, b.qubits.data(), nullptr, 0);
+                else r = apply_fused(st, U.data(), k, b.qubits.data());
+            }
+            if (r) return r;
+            r = after((int)b.ops.size());
+            if (r) return r;
+        }
+    }
+    if (R > 0 && st->gates_since_renorm > 0) return renorm(st);
+    return SV_OK;
+}
+
+sv_status sv_norm(sv_state st, double *out) {
+    if (!st || !out) return fail(SV_E_INVALID, "null argument");
+    sv_status r = norm_device(st);
+    if (r) return r;
+    SV_HIP(hipMemcpyAsync(out, svk::norm2_dev_ptr(st->ws, st->n), sizeof(double), hipMemcpyDeviceToHost, st->stream));
+    SV_HIP(hipStreamSynchronize(st->stream));
+    return SV_OK;
+}
+
+sv_status sv_renormalize(sv_state st) {
+    if (!st) return fail(SV_E_INVALID, "null state");
+    return renorm(st);
+}
+
+sv_status sv_sample(sv_state st, int64_t shots, uint64_t seed, uint64_t *out) {
+    if (!st) return fail(SV_E_INVALID, "null state");
+    if (shots < 0) return fail(SV_E_INVALID, "shots < 0");
+    if (shots == 0) return SV_OK;
+    if (!out) return fail(SV_E_INVALID, "null output");
+    sv_ctx c = st->ctx;
+    {
+        TraceScope ts(&c->tracer, st->stream, "cdf", (double)st->bytes);
+        SV_HIP(svk::launch_cdf(st->psi, st->n, st->is_c64(), st->ws, st->stream));
+    }
+    double total = 0;
+    SV_HIP(hipMemcpyAsync(&total, svk::norm2_dev_ptr(st->ws, st->n), sizeof(double), hipMemcpyDeviceToHost,
+                          st->stream));
+    int64_t chunk = std::min<int64_t>(shots, 1 << 22);
+    uint64_t *dev = nullptr;
+    while (!(dev = (uint64_t *)c->arena.alloc(chunk * sizeof(uint64_t)))) {
+        if (chunk <= 1024) return fail(SV_E_OOM, "arena cannot hold the shot buffer");
+        chunk /= 2;
+    }
+    sv_status r = SV_OK;
+    const double sbytes = 1024.0 * (st->is_c64() ? 8 : 16);
+    for (int64_t s0 = 0; s0 < shots && r == SV_OK; s0 += chunk) {
+        const int64_t cnt = std::min(chunk, shots - s0);
+        hipError_t e;
+        {
+            TraceScope ts(&c->tracer, st->stream, "sample", sbytes * cnt);
+            e = svk::launch_sample(st->psi, st->n, st->is_c64(), st->ws, cnt, seed, (uint64_t)s0, dev, st->stream);
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(out + s0, dev, cnt * sizeof(uint64_t), hipMemcpyDeviceToHost, st->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+        if (e != hipSuccess) r = hip_fail(e, "sampling");
+    }
+    c->arena.free(dev);
+    if (r == SV_OK && !(total > 0.0)) return fail(SV_E_NUMERIC, "state has zero norm");
+    return r;
+}
+
+sv_status sv_expect(sv_state st, const sv_pauli *terms, int nterms, double *out_each, double *out_weighted) {
+    if (!st || (nterms > 0 && !terms) || nterms < 0) return fail(SV_E_INVALID, "bad argument");
+    const uint64_t full = st->n == 64 ? ~0ull : ((1ull << st->n) - 1);
+    for (int t = 0; t < nterms; ++t)
+        if ((terms[t].xmask | terms[t].zmask) & ~full) return fail(SV_E_INVALID, "Pauli mask beyond n qubits");
+    std::vector<int> zi, xi;
+    for (int t = 0; t < nterms; ++t) (terms[t].xmask ? xi : zi).push_back(t);
+    const int TB = 16;
+    const int nzb = (int)((zi.size() + TB - 1) / TB);
+    // device buffers: z masks per batch (TB each), z results (TB+1 per batch), xz results (2 per term)
+    const uint64_t nres = (uint64_t)std::max(1, nzb) * (TB + 1) + 2 * xi.size() + 1;
+    const uint64_t nmask = (uint64_t)std::max(1, nzb) * TB;
+    sv_ctx c = st->ctx;
+    char *buf = (char *)c->arena.alloc(8 * (nres + nmask));
+    if (!buf) return fail(SV_E_OOM, "arena cannot hold the expectation buffers");
+    double *res = (double *)buf;
+    uint64_t *masks = (uint64_t *)(buf + 8 * nres);
+    std::vector<uint64_t> hmask(nmask, 0);
+    for (size_t i = 0; i < zi.size(); ++i) hmask[i] = terms[zi[i]].zmask;
+    std::vector<double> hres(nres, 0.0);
+    sv_status r = SV_OK;
+    hipError_t e = hipMemcpyAsync(masks, hmask.data(), 8 * nmask, hipMemcpyHostToDevice, st->stream);
+    // a Z batch always runs (it also yields the squared norm)
+    for (int b = 0; b < std::max(1, nzb) && e == hipSuccess; ++b) {
+        const int cnt = std::min<int>(TB, (int)zi.size() - b * TB);
+        TraceScope ts(&c->tracer, st->stream, "expect_z", (double)st->bytes);
+        e = svk::launch_expect_z(st->psi, st->n, st->is_c64(), masks + b * TB, std::max(cnt, 0), st->ws,
+                                 res + b * (TB + 1), st->stream);
+    }
+    for (size_t i = 0; i < xi.size() && e == hipSuccess; ++i) {
+        TraceScope ts(&c->tracer, st->stream, "expect_xz", (double)st->bytes);
+        e = svk::launch_expect_xz(st->psi, st->n, st->is_c64(), terms[xi[i]].xmask, terms[xi[i]].zmask, st->ws,
+                                  res + std::max(1, nzb) * (TB + 1) + 2 * i, st->stream);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(hres.data(), res, 8 * nres, hipMemcpyDeviceToHost, st->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+    c->arena.free(buf);
+    if (e != hipSuccess) return hip_fail(e, "expectation");
+    // the squared norm comes with the first Z batch, after its cnt term slots
+    const int cnt0 = std::min<int>(TB, (int)zi.size());
+    const double norm2 = hres[std::max(cnt0, 0)];
+    if (!(norm2 > 0.0)) return fail(SV_E_NUMERIC, "state has zero norm");
+    std::vector<double> vals(nterms, 0.0);
+    for (size_t i = 0; i < zi.size(); ++i) {
+        const int b = (int)(i / TB), j = (int)(i % TB);
+        vals[zi[i]] = hres[b * (TB + 1) + j] / norm2;
+    }
+    for (size_t i = 0; i < xi.size(); ++i) vals[xi[i]] = hres[std::max(1, nzb) * (TB + 1) + 2 * i] / norm2;
+    double wsum = 0.0;
+    for (int t = 0; t < nterms; ++t) {
+        if (out_each) out_each[t] = vals[t];
+        wsum += terms[t].coeff * vals[t];
+    }
+    if (out_weighted) *out_weighted = wsum;
+    return r;
+}
+
+sv_status sv_trace_enable(sv_ctx c, int on) {
+    if (!c) return fail(SV_E_INVALID, "null context");
+    std::lock_guard<std::mutex> g(c->tracer.mu);
+    c->tracer.on = on != 0;
+    return SV_OK;
+}
+
+sv_status sv_trace_read(sv_ctx c, sv_trace_rec *out, int cap, int *count) {
+    if (!c) return fail(SV_E_INVALID, "null context");
+    std::lock_guard<std::mutex> g(c->tracer.mu);
+    for (auto &p : c->tracer.pending) {
+        hipEventSynchronize(p.b);
+        float ms = 0;
+        hipEventElapsedTime(&ms, p.a, p.b);
+        auto &a = c->tracer.agg[p.name];
+        a.launches++;
+        a.seconds += ms * 1e-3;
+        a.bytes += p.bytes;
+        c->tracer.pool.push_back(p.a);
+        c->tracer.pool.push_back(p.b);
+    }
+    c->tracer.pending.clear();
+    int i = 0;
+    for (auto &kv : c->tracer.agg) {
+        if (i < cap && out) {
+            memset(&out[i], 0, sizeof(sv_trace_rec));
+            strncpy(out[i].name, kv.first.c_str(), sizeof(out[i].name) - 1);
+            out[i].launches = kv.second.launches;
+            out[i].seconds = kv.second.seconds;
+            out[i].bytes = kv.second.bytes;
+        }
+        ++i;
+    }
+    if (count) *count = i;
+    c->tracer.agg.clear();
+    return SV_OK;
+}
+
+}  // extern "C"

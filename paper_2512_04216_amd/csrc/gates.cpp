@@ -1,0 +1,324 @@
+// gates.cpp -- gate matrices, gate classification and the fusion planner
+// (host side of the state-vector library).
+//
+// Gate matrices follow Qiskit's definitions (the paper takes Qiskit and
+// OpenQASM2 circuits as input, Sec. III-A), global phase included. A gate is
+// classified by exact comparisons on its matrix so that each launch reads and
+// writes only the amplitudes the gate changes: a single phase on a subspace
+// (S, T, P, Z, CZ, CP), a general diagonal (RZ, RZZ), a two-level unitary (any
+// one-qubit gate, CX, CY, SWAP, CCX) or a dense two-qubit matrix.
+#include "sv_host.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace svh {
+
+static const cd I1(0.0, 1.0);
+
+int gate_nqubits(int kind) {
+    switch (kind) {
+    case SV_GATE_CX: case SV_GATE_CY: case SV_GATE_CZ: case SV_GATE_CP:
+    case SV_GATE_SWAP: case SV_GATE_RZZ:
+        return 2;
+    case SV_GATE_CCX:
+        return 3;
+    default:
+        return (kind >= 0 && kind < SV_GATE_COUNT) ? 1 : -1;
+    }
+}
+
+bool gate_matrix(int kind, const double *p, bool adjoint, cd *U, int *k, int *nc) {
+    for (int i = 0; i < 16; ++i) U[i] = 0.0;
+    *nc = 0;
+    *k = 1;
+    const double r2 = 1.0 / std::sqrt(2.0);
+    auto set2 = [&](cd a, cd b, cd c, cd d) {
+        U[0] = a; U[1] = b; U[2] = c; U[3] = d;
+    };
+    auto half = [&](double t, double &c, double &s) {
+        c = std::cos(0.5 * t);
+        s = std::sin(0.5 * t);
+    };
+    double c, s;
+    switch (kind) {
+    case SV_GATE_H: set2(r2, r2, r2, -r2); break;
+    case SV_GATE_X: set2(0.0, 1.0, 1.0, 0.0); break;
+    case SV_GATE_Y: set2(0.0, -I1, I1, 0.0); break;
+    case SV_GATE_Z: set2(1.0, 0.0, 0.0, -1.0); break;
+    case SV_GATE_S: set2(1.0, 0.0, 0.0, I1); break;
+    case SV_GATE_SDG: set2(1.0, 0.0, 0.0, -I1); break;
+    case SV_GATE_T: set2(1.0, 0.0, 0.0, std::polar(1.0, M_PI / 4)); break;
+    case SV_GATE_TDG: set2(1.0, 0.0, 0.0, std::polar(1.0, -M_PI / 4)); break;
+    case SV_GATE_SX: set2(cd(0.5, 0.5), cd(0.5, -0.5), cd(0.5, -0.5), cd(0.5, 0.5)); break;
+    case SV_GATE_RX: half(p[0], c, s); set2(c, -I1 * s, -I1 * s, c); break;
+    case SV_GATE_RY: half(p[0], c, s); set2(c, -s, s, c); break;
+    case SV_GATE_RZ: set2(std::polar(1.0, -0.5 * p[0]), 0.0, 0.0, std::polar(1.0, 0.5 * p[0])); break;
+    case SV_GATE_P: set2(1.0, 0.0, 0.0, std::polar(1.0, p[0])); break;
+    case SV_GATE_U3:
+        half(p[0], c, s);
+        set2(c, -std::polar(1.0, p[2]) * s, std::polar(1.0, p[1]) * s, std::polar(1.0, p[1] + p[2]) * c);
+        break;
+    case SV_GATE_CX: *nc = 1; set2(0.0, 1.0, 1.0, 0.0); break;
+    case SV_GATE_CY: *nc = 1; set2(0.0, -I1, I1, 0.0); break;
+    case SV_GATE_CZ: *nc = 1; set2(1.0, 0.0, 0.0, -1.0); break;
+    case SV_GATE_CP: *nc = 1; set2(1.0, 0.0, 0.0, std::polar(1.0, p[0])); break;
+    case SV_GATE_CCX: *nc = 2; set2(0.0, 1.0, 1.0, 0.0); break;
+    case SV_GATE_SWAP:
+        *k = 2;
+        U[0] = 1.0; U[1 * 4 + 2] = 1.0; U[2 * 4 + 1] = 1.0; U[15] = 1.0;
+        break;
+    case SV_GATE_RZZ: {
+        *k = 2;
+        const cd a = std::polar(1.0, -0.5 * p[0]), b = std::polar(1.0, 0.5 * p[0]);
+        U[0] = a; U[5] = b; U[10] = b; U[15] = a;
+        break;
+    }
+    default:
+        return false;
+    }
+    if (adjoint) {
+        const int K = 1 << *k;
+        cd A[16];
+        for (int r = 0; r < K; ++r)
+            for (int q = 0; q < K; ++q) A[r * K + q] = std::conj(U[q * K + r]);
+        for (int i = 0; i < K * K; ++i) U[i] = A[i];
+    }
+    return true;
+}
+
+// ---- classification -------------------------------------------------------------
+
+static uint64_t qubit_bits(int pattern, const int *targets, int k) {
+    uint64_t m = 0;
+    for (int j = 0; j < k; ++j)
+        if ((pattern >> j) & 1) m |= 1ull << targets[j];
+    return m;
+}
+
+static double group_bytes(int n, int s, int K, uint64_t fm) {
+    return 2.0 * s * std::ldexp(1.0, n + K - __builtin_popcountll(fm));
+}
+
+static const char *group_name(int K, uint64_t F0, uint64_t F1, int lb) {
+    const uint64_t low = (1ull << lb) - 1;
+    if (K == 0) return "group_phase";
+    if (K == 1) {
+        const bool h = F0 & ~low, l = F0 & low;
+        return (h && l) ? "group_mix" : (h ? "group_h1" : "group_l1");
+    }
+    const int nh = ((F0 & ~low) != 0) + ((F1 & ~low) != 0);
+    return nh == 2 ? "group_h2" : (nh == 1 ? "group_h1l1" : "group_l2");
+}
+
+sv_status apply_matrix(sv_state st, const cd *U, int k, const int *targets, const int *controls, int nc) {
+    const int K = 1 << k;
+    const int s = st->is_c64() ? 8 : 16;
+    const int lb = svk::low_bits(st->is_c64());
+    uint64_t cmask = 0, tmask = 0;
+    for (int j = 0; j < nc; ++j) cmask |= 1ull << controls[j];
+    for (int j = 0; j < k; ++j) tmask |= 1ull << targets[j];
+    bool diag = true;
+    for (int r = 0; r < K && diag; ++r)
+        for (int q = 0; q < K; ++q)
+            if (r != q && U[r * K + q] != 0.0) {
+                diag = false;
+                break;
+            }
+    Tracer *tr = &st->ctx->tracer;
+    if (diag) {
+        int nonunit = 0, which = -1;
+        for (int m = 0; m < K; ++m)
+            if (U[m * K + m] != 1.0) {
+                ++nonunit;
+                which = m;
+            }
+        if (nonunit == 0) return SV_OK;
+        if (nonunit == 1) {
+            svk::GroupGate g;
+            g.fm = cmask | tmask;
+            g.fv = cmask | qubit_bits(which, targets, k);
+            g.K = 0;
+            g.U[0] = U[which * K + which].real();
+            g.U[1] = U[which * K + which].imag();
+            TraceScope ts(tr, st->stream, "group_phase", group_bytes(st->n, s, 0, g.fm));
+            SV_HIP(svk::launch_group(g, st->psi, st->n, st->is_c64(), st->stream));
+            return SV_OK;
+        }
+        svk::DiagGate g;
+        g.cmask = cmask;
+        g.k = k;
+        for (int j = 0; j < k; ++j) g.targets[j] = targets[j];
+        for (int m = 0; m < K; ++m) {
+            g.d[2 * m] = U[m * K + m].real();
+            g.d[2 * m + 1] = U[m * K + m].imag();
+        }
+        TraceScope ts(tr, st->stream, "diag", 2.0 * s * std::ldexp(1.0, st->n - __builtin_popcountll(cmask)));
+        SV_HIP(svk::launch_diag(g, st->psi, st->n, st->is_c64(), st->stream));
+        return SV_OK;
+    }
+    // two-level: identity outside two basis states
+    std::vector<int> active;
+    for (int m = 0; m < K; ++m) {
+        bool ident = true;
+        for (int q = 0; q < K; ++q) {
+            const cd want = (m == q) ? cd(1.0) : cd(0.0);
+            if (U[m * K + q] != want || U[q * K + m] != want) {
+                ident = false;
+                break;
+            }
+        }
+        if (!ident) active.push_back(m);
+    }
+    if (active.size() == 2) {
+        const int p0 = active[0], p1 = active[1];
+        svk::GroupGate g;
+        g.fm = cmask | tmask;
+        g.fv = cmask | qubit_bits(p0, targets, k);
+        g.K = 1;
+        g.F[0] = qubit_bits(p0 ^ p1, targets, k);
+        const cd u2[4] = {U[p0 * K + p0], U[p0 * K + p1], U[p1 * K + p0], U[p1 * K + p1]};
+        for (int i = 0; i < 4; ++i) {
+            g.U[2 * i] = u2[i].real();
+            g.U[2 * i + 1] = u2[i].imag();
+        }
+        TraceScope ts(tr, st->stream, group_name(1, g.F[0], 0, lb), group_bytes(st->n, s, 1, g.fm));
+        SV_HIP(svk::launch_group(g, st->psi, st->n, st->is_c64(), st->stream));
+        return SV_OK;
+    }
+    if (k == 2) {
+        svk::GroupGate g;
+        g.fm = cmask | tmask;
+        g.fv = cmask;
+        g.K = 2;
+        g.F[0] = 1ull << targets[0];
+        g.F[1] = 1ull << targets[1];
+        for (int i = 0; i < 16; ++i) {
+            g.U[2 * i] = U[i].real();
+            g.U[2 * i + 1] = U[i].imag();
+        }
+        TraceScope ts(tr, st->stream, group_name(2, g.F[0], g.F[1], lb), group_bytes(st->n, s, 2, g.fm));
+        SV_HIP(svk::launch_group(g, st->psi, st->n, st->is_c64(), st->stream));
+        return SV_OK;
+    }
+    // dense k >= 3 (or a dense 1-qubit gate would have been two-level)
+    if (nc == 0) return apply_fused(st, U, k, targets);
+    // controlled dense block: embed the controls as extra targets
+    const int kk = k + nc;
+    if (kk > SV_MAX_FUSED) return fail(SV_E_UNSUPPORTED, "controlled dense gate wider than 5 qubits");
+    const int KK = 1 << kk;
+    std::vector<cd> W(KK * KK, 0.0);
+    for (int m = 0; m < KK; ++m) W[m * KK + m] = 1.0;
+    const int off = KK - K;   // all control bits (the high bits) set
+    for (int r = 0; r < K; ++r)
+        for (int q = 0; q < K; ++q) W[(off + r) * KK + off + q] = U[r * K + q];
+    int tg[SV_MAX_FUSED];
+    for (int j = 0; j < k; ++j) tg[j] = targets[j];
+    for (int j = 0; j < nc; ++j) tg[k + j] = controls[j];
+    return apply_fused(st, W.data(), kk, tg);
+}
+
+// ---- fusion planner --------------------------------------------------------------
+// DAG-aware greedy grouping: open blocks hold disjoint qubit sets. A gate joins
+// the open block(s) its qubits meet if the union stays within fuse_k qubits
+// (open blocks it meets are merged; gates of disjoint blocks commute, so the
+// merged order is still valid); otherwise those blocks are closed and emitted
+// and the gate opens a new block. Every gate is placed after all earlier gates
+// that share a qubit with it, so the emitted order is a valid schedule.
+std::vector<Block> plan_fusion(const sv_op *ops, int nops, int fuse_k) {
+    struct Open {
+        uint64_t q;
+        std::vector<int> ops;
+        int order;
+    };
+    std::vector<Open> open;
+    std::vector<Block> out;
+    int counter = 0;
+    auto emit = [&](Open &o) {
+        Block b;
+        b.ops = o.ops;
+        std::sort(b.ops.begin(), b.ops.end());
+        for (int p = 0; p < 64; ++p)
+            if ((o.q >> p) & 1) b.qubits.push_back(p);
+        out.push_back(std::move(b));
+    };
+    for (int i = 0; i < nops; ++i) {
+        uint64_t g = 0;
+        const int nq = gate_nqubits(ops[i].kind);
+        for (int j = 0; j < nq; ++j) g |= 1ull << ops[i].q[j];
+        uint64_t uni = g;
+        std::vector<int> hit;
+        for (int b = 0; b < (int)open.size(); ++b)
+            if (open[b].q & g) {
+                hit.push_back(b);
+                uni |= open[b].q;
+            }
+        if (__builtin_popcountll(uni) <= fuse_k) {
+            Open merged{uni, {}, counter++};
+            for (int b : hit) merged.ops.insert(merged.ops.end(), open[b].ops.begin(), open[b].ops.end());
+            merged.ops.push_back(i);
+            for (int h = (int)hit.size() - 1; h >= 0; --h) open.erase(open.begin() + hit[h]);
+            open.push_back(std::move(merged));
+        } else {
+            // close the blocks the gate meets, oldest first
+            std::sort(hit.begin(), hit.end(), [&](int a, int b) { return open[a].order < open[b].order; });
+            for (int b : hit) emit(open[b]);
+            std::vector<int> idx = hit;
+            std::sort(idx.begin(), idx.end());
+            for (int h = (int)idx.size() - 1; h >= 0; --h) open.erase(open.begin() + idx[h]);
+            open.push_back(Open{g, {i}, counter++});
+        }
+    }
+    std::sort(open.begin(), open.end(), [](const Open &a, const Open &b) { return a.order < b.order; });
+    for (auto &o : open) emit(o);
+    return out;
+}
+
+// Block matrix: apply every gate of the block to each basis column of the
+// 2^k identity (a tiny state-vector pass on the host, complex128).
+void block_matrix(const sv_op *ops, const Block &b, std::vector<cd> &U) {
+    const int k = (int)b.qubits.size();
+    const int K = 1 << k;
+    int pos[64];
+    for (int j = 0; j < k; ++j) pos[b.qubits[j]] = j;
+    U.assign((size_t)K * K, 0.0);
+    std::vector<cd> col(K);
+    for (int c = 0; c < K; ++c) {
+        std::fill(col.begin(), col.end(), cd(0.0));
+        col[c] = 1.0;
+        for (int oi : b.ops) {
+            const sv_op &o = ops[oi];
+            cd G[16];
+            int gk, nc;
+            gate_matrix(o.kind, o.p, o.flags & SV_OP_ADJOINT, G, &gk, &nc);
+            const int GK = 1 << gk;
+            int tg[3], cl[3];
+            for (int j = 0; j < nc; ++j) cl[j] = pos[o.q[j]];
+            for (int j = 0; j < gk; ++j) tg[j] = pos[o.q[nc + j]];
+            uint64_t tm = 0, cm = 0;
+            for (int j = 0; j < gk; ++j) tm |= 1ull << tg[j];
+            for (int j = 0; j < nc; ++j) cm |= 1ull << cl[j];
+            for (int i = 0; i < K; ++i) {
+                if ((i & tm) || (i & cm) != cm) continue;
+                cd v[4];
+                int idx[4];
+                for (int m = 0; m < GK; ++m) {
+                    int a = i;
+                    for (int j = 0; j < gk; ++j)
+                        if ((m >> j) & 1) a |= 1 << tg[j];
+                    idx[m] = a;
+                    v[m] = col[a];
+                }
+                for (int r = 0; r < GK; ++r) {
+                    cd w = 0.0;
+                    for (int m = 0; m < GK; ++m) w += G[r * GK + m] * v[m];
+                    col[idx[r]] = w;
+                }
+            }
+        }
+        for (int r = 0; r < K; ++r) U[(size_t)r * K + c] = col[r];
+    }
+}
+
+}  // namespace svh

@@ -1,0 +1,590 @@
+// k_measure.hip -- FP64 measurement kernels for gfx950: squared norm, the
+// cumulative distribution used for shot sampling, shot resolution and Pauli
+// expectation values.
+//
+// Sec. III-B of the paper simulates a circuit once and then draws every shot
+// from the final state, and evaluates expectation values on that cached state.
+// Here the probabilities |psi_i|^2 are formed in FP64 (exact squares for
+// complex64 amplitudes), summed per 1024-amplitude leaf, the leaf sums are
+// scanned with compensated (TwoSum) arithmetic into a leaf CDF, and each shot
+// binary-searches the leaf CDF and then scans one leaf. All reductions use a
+// fixed tree that depends only on n, so results are bitwise reproducible.
+#include "sv_device.h"
+#include "sv_kernels.h"
+
+#include <algorithm>
+
+using namespace svd;
+
+namespace {
+
+constexpr int kLeafBits = 10;           // amplitudes per leaf = 1024
+constexpr int kChunk = 1024;            // leaves per scan chunk
+constexpr int kScanThreads = 256;
+constexpr int kMaxRedBlocks = 1024;     // partial sums of a reduction
+constexpr int kTB = 16;                 // Z terms per reduction pass
+
+struct WS {
+    uint64_t nleaf, nchunk, nred;
+    uint64_t off_leafsum, off_leafcdf, off_chunk, off_chunkpre, off_part, off_res;
+};
+
+__host__ __device__ inline uint64_t nleaf_of(int n) { return n > kLeafBits ? (1ull << (n - kLeafBits)) : 1ull; }
+
+inline WS ws_layout(int n) {
+    WS w;
+    w.nleaf = nleaf_of(n);
+    w.nchunk = (w.nleaf + kChunk - 1) / kChunk;
+    // reduction blocks: about 8 segment-units per wave, 4 waves per block
+    const uint64_t units = n > 6 ? (1ull << (n - 6)) : 1ull;
+    w.nred = std::min<uint64_t>(kMaxRedBlocks, std::max<uint64_t>(1, units / 32));
+    w.off_leafsum = 0;
+    w.off_leafcdf = w.off_leafsum + w.nleaf;
+    w.off_chunk = w.off_leafcdf + w.nleaf + 1;
+    w.off_chunkpre = w.off_chunk + 2 * w.nchunk;
+    w.off_part = w.off_chunkpre + 2 * w.nchunk;
+    w.off_res = w.off_part + w.nred * (kTB + 1) * 2;
+    return w;
+}
+
+inline uint64_t ws_doubles(int n) {
+    WS w = ws_layout(n);
+    return w.off_res + 2 * (kTB + 1) + 8;
+}
+
+// SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): output s (from 0) of the
+// generator seeded with `seed` is the variant-13 finaliser applied to
+// seed + (s + 1) * 0x9E3779B97F4A7C15.
+__device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t s) {
+    uint64_t z = seed + (s + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ inline double u01_at(uint64_t seed, uint64_t s) {
+    return (double)(splitmix64_at(seed, s) >> 11) * 0x1.0p-53;
+}
+
+template <typename T>
+__device__ inline double prob(const Q &q, int r) {
+    const Cx<T> a = Amp<T>::get(q, r);
+    const double re = (double)a.re, im = (double)a.im;
+    return fma(re, re, im * im);
+}
+
+// ---- leaf sums ---------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_leafsum(const u4 *__restrict__ psi, int n, double *__restrict__ leafsum) {
+    constexpr int E = Amp<T>::E;
+    const uint64_t leaf = wave_id_global();
+    const uint64_t nleaf = nleaf_of(n);
+    if (leaf >= nleaf) return;
+    const int lane = threadIdx.x & 63;
+    const uint64_t leaf_amps = n > kLeafBits ? (1ull << kLeafBits) : (1ull << n);
+    const uint64_t nvec = (leaf_amps + E - 1) / E;
+    const u4 *p = psi + leaf * ((1ull << kLeafBits) / E);
+    DD acc = dd_zero();
+    for (uint64_t vi = lane; vi < nvec; vi += 64) {
+        Q q;
+        q.v = p[vi];
+#pragma unroll
+        for (int r = 0; r < E; ++r) neum_add(acc, prob<T>(q, r));
+    }
+    acc = wave_reduce_dd(acc, lane);
+    if (lane == 0) leafsum[leaf] = dd_value(acc);
+}
+
+// Block-wide exclusive scan of compensated values (Hillis-Steele in LDS;
+// the combination order is fixed).
+__device__ inline DD block_exclusive_scan(DD v, DD *total) {
+    __shared__ double ss[kScanThreads], sc[kScanThreads];
+    const int t = threadIdx.x;
+    ss[t] = v.s;
+    sc[t] = v.c;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        DD mine{ss[t], sc[t]};
+        DD other = dd_zero();
+        if (t >= off) other = DD{ss[t - off], sc[t - off]};
+        __syncthreads();
+        if (t >= off) mine = dd_add(other, mine);
+        ss[t] = mine.s;
+        sc[t] = mine.c;
+        __syncthreads();
+    }
+    DD incl{ss[t], sc[t]};
+    *total = DD{ss[kScanThreads - 1], sc[kScanThreads - 1]};
+    DD excl = dd_zero();
+    if (t > 0) excl = DD{ss[t - 1], sc[t - 1]};
+    __syncthreads();
+    (void)incl;
+    return excl;
+}
+
+// Chunk totals: chunk c covers leaves [c*kChunk, (c+1)*kChunk).
+__global__ __launch_bounds__(kScanThreads) void k_chunk_total(const double *__restrict__ leafsum, uint64_t nleaf,
+                                                              double *__restrict__ chunk) {
+    constexpr int PER = kChunk / kScanThreads;
+    const uint64_t c = blockIdx.x;
+    DD v = dd_zero();
+    for (int i = 0; i < PER; ++i) {
+        const uint64_t leaf = c * kChunk + (uint64_t)threadIdx.x * PER + i;
+        if (leaf < nleaf) neum_add(v, leafsum[leaf]);
+    }
+    DD total;
+    block_exclusive_scan(v, &total);
+    if (threadIdx.x == 0) {
+        chunk[2 * c] = total.s;
+        chunk[2 * c + 1] = total.c;
+    }
+}
+
+// Exclusive prefix of the chunk totals (one workgroup).
+__global__ __launch_bounds__(kScanThreads) void k_chunk_scan(const double *__restrict__ chunk, uint64_t nchunk,
+                                                             double *__restrict__ chunkpre, double *__restrict__ res) {
+    const uint64_t per = (nchunk + kScanThreads - 1) / kScanThreads;
+    const uint64_t b0 = (uint64_t)threadIdx.x * per;
+    DD v = dd_zero();
+    for (uint64_t i = b0; i < b0 + per && i < nchunk; ++i) v = dd_add(v, DD{chunk[2 * i], chunk[2 * i + 1]});
+    DD total;
+    DD run = block_exclusive_scan(v, &total);
+    for (uint64_t i = b0; i < b0 + per && i < nchunk; ++i) {
+        chunkpre[2 * i] = run.s;
+        chunkpre[2 * i + 1] = run.c;
+        run = dd_add(run, DD{chunk[2 * i], chunk[2 * i + 1]});
+    }
+    if (threadIdx.x == 0) res[0] = dd_value(total);
+}
+
+// Leaf CDF: leafcdf[l] = sum of the leaves before l; leafcdf[nleaf] = total.
+__global__ __launch_bounds__(kScanThreads) void k_leaf_scan(const double *__restrict__ leafsum, uint64_t nleaf,
+                                                            const double *__restrict__ chunkpre,
+                                                            const double *__restrict__ res,
+                                                            double *__restrict__ leafcdf) {
+    constexpr int PER = kChunk / kScanThreads;
+    const uint64_t c = blockIdx.x;
+    const uint64_t l0 = c * kChunk + (uint64_t)threadIdx.x * PER;
+    DD v = dd_zero();
+    for (int i = 0; i < PER; ++i)
+        if (l0 + i < nleaf) neum_add(v, leafsum[l0 + i]);
+    DD total;
+    DD run = block_exclusive_scan(v, &total);
+    run = dd_add(DD{chunkpre[2 * c], chunkpre[2 * c + 1]}, run);
+    for (int i = 0; i < PER; ++i) {
+        if (l0 + i < nleaf) {
+            leafcdf[l0 + i] = dd_value(run);
+            neum_add(run, leafsum[l0 + i]);
+        }
+    }
+    if (c == 0 && threadIdx.x == 0) leafcdf[nleaf] = res[0];
+}
+
+// ---- shot resolution ---------------------------------------------------
+__device__ inline double wave_incl_scan(double v, int lane) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int src = lane >= off ? lane - off : lane;
+        union {
+            double d;
+            int w[2];
+        } u;
+        u.d = v;
+        u.w[0] = __builtin_amdgcn_ds_bpermute(src << 2, u.w[0]);
+        u.w[1] = __builtin_amdgcn_ds_bpermute(src << 2, u.w[1]);
+        if (lane >= off) v = u.d + v;
+    }
+    return v;
+}
+
+__device__ inline double read_lane_d(double v, int l) {
+    union {
+        double d;
+        int w[2];
+    } u;
+    u.d = v;
+    u.w[0] = __builtin_amdgcn_readlane(u.w[0], l);
+    u.w[1] = __builtin_amdgcn_readlane(u.w[1], l);
+    return u.d;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sample(const u4 *__restrict__ psi, int n, const double *__restrict__ leafcdf,
+                                                int64_t shots, uint64_t seed, uint64_t s0, uint64_t *__restrict__ out) {
+    constexpr int E = Amp<T>::E;
+    const uint64_t sl = wave_id_global();
+    if (sl >= (uint64_t)shots) return;
+    const uint64_t s = s0 + sl;
+    const int lane = threadIdx.x & 63;
+    const uint64_t nleaf = nleaf_of(n);
+    const double total = leafcdf[nleaf];
+    const double r = u01_at(seed, s) * total;
+    // first leaf whose end exceeds r
+    uint64_t lo = 0, hi = nleaf;
+    while (lo < hi) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        if (leafcdf[mid + 1] > r) hi = mid;
+        else lo = mid + 1;
+    }
+    bool clamp = false;
+    if (lo == nleaf) {
+        // rounding left r at the total: use the last leaf that has mass
+        uint64_t a = 0, b = nleaf - 1;
+        while (a < b) {
+            const uint64_t mid = a + (b - a) / 2;
+            if (leafcdf[mid + 1] >= total) b = mid;
+            else a = mid + 1;
+        }
+        lo = a;
+        clamp = true;
+    }
+    const uint64_t leaf = lo;
+    const double rl = r - leafcdf[leaf];
+    const uint64_t leaf_amps = n > kLeafBits ? (1ull << kLeafBits) : (1ull << n);
+    const uint64_t nvec = (leaf_amps + E - 1) / E;
+    const u4 *p = psi + leaf * ((1ull << kLeafBits) / E);
+    double carry = 0.0;
+    int64_t found = -1, lastnz = -1;
+    for (uint64_t row = 0; row * 64 < nvec; ++row) {
+        const uint64_t vi = row * 64 + lane;
+        double pr[E];
+        Q q;
+        q.v = u4{0, 0, 0, 0};
+        if (vi < nvec) q.v = p[vi];
+        double lt = 0.0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            pr[e] = prob<T>(q, e);
+            lt += pr[e];
+        }
+        const double incl = wave_incl_scan(lt, lane);
+        const double excl = incl - lt;   // not used for the decision below
+        (void)excl;
+        // exclusive prefix = inclusive of the previous lane
+        double prev = 0.0;
+        {
+            const int src = lane > 0 ? lane - 1 : 0;
+            union {
+                double d;
+                int w[2];
+            } u;
+            u.d = incl;
+            u.w[0] = __builtin_amdgcn_ds_bpermute(src << 2, u.w[0]);
+            u.w[1] = __builtin_amdgcn_ds_bpermute(src << 2, u.w[1]);
+            prev = lane > 0 ? u.d : 0.0;
+        }
+        int hit = -1;
+        double run = carry + prev;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            run += pr[e];
+            if (hit < 0 && run > rl) hit = e;
+        }
+        int lastnz_e = -1;
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            if (pr[e] > 0.0) lastnz_e = e;
+        const uint64_t hitmask = __ballot(!clamp && hit >= 0);
+        const uint64_t nzmask = __ballot(lastnz_e >= 0);
+        if (nzmask) {
+            const int l = 63 - __clzll(nzmask);
+            const int le = __builtin_amdgcn_readlane(lastnz_e, l);
+            lastnz = (int64_t)(row * 64 + l) * E + le;
+        }
+        if (hitmask) {
+            const int l = __ffsll((long long)hitmask) - 1;
+            const int he = __builtin_amdgcn_readlane(hit, l);
+            found = (int64_t)(row * 64 + l) * E + he;
+            break;
+        }
+        carry += read_lane_d(incl, 63);
+    }
+    if (found < 0) found = lastnz < 0 ? 0 : lastnz;
+    if (lane == 0) out[sl] = leaf * (1ull << kLeafBits) + (uint64_t)found;
+}
+
+// ---- reductions: norm and Z-only Pauli batch ---------------------------
+// A "row" is one 16-byte load per lane (64 * E consecutive amplitudes). For a
+// Z term t the sign of amplitude i is (-1)^{popc(i & z_t)}; i = rowbase + lane*E + e
+// splits the parity into a lane-constant part and a part that is uniform for
+// the (row, e) pair. Per lane we keep, for every term, the sum S_t of p over the
+// (row, e) pairs whose uniform parity is 1, and the plain total P; the lane's
+// signed sum is then P - 2 S_t if its own parity bit is 0, and 2 S_t - P if 1.
+template <typename T>
+__global__ __launch_bounds__(256) void k_zbatch(const u4 *__restrict__ psi, int n, const uint64_t *__restrict__ zm_g,
+                                                int nterms, uint64_t nred, double *__restrict__ part) {
+    constexpr int E = Amp<T>::E;
+    const int lane = threadIdx.x & 63;
+    const uint64_t nvec = (1ull << n) >= (uint64_t)E ? (1ull << n) / E : 1ull;
+    const uint64_t nrows = (nvec + 63) / 64;
+    const uint64_t nwaves = nred * 4;
+    const uint64_t w = wave_id_global();
+    uint64_t zm[kTB];
+    uint32_t lanebits = 0;
+#pragma unroll
+    for (int t = 0; t < kTB; ++t) {
+        zm[t] = t < nterms ? zm_g[t] : 0;
+        lanebits |= (uint32_t)(__popcll(((uint64_t)lane * E) & zm[t]) & 1) << t;
+    }
+    DD P = dd_zero();
+    DD S[kTB];
+#pragma unroll
+    for (int t = 0; t < kTB; ++t) S[t] = dd_zero();
+    // contiguous row range per wave (fixed by n)
+    const uint64_t per = (nrows + nwaves - 1) / nwaves;
+    const uint64_t r0 = w * per, r1 = std::min<uint64_t>(nrows, r0 + per);
+    constexpr int CH = 8;   // rows per plain-double partial
+    for (uint64_t rb = r0; rb < r1; rb += CH) {
+        double pP = 0.0;
+        double pS[kTB];
+#pragma unroll
+        for (int t = 0; t < kTB; ++t) pS[t] = 0.0;
+        Q q[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const uint64_t vi = (rb + k) * 64 + lane;
+            q[k].v = u4{0, 0, 0, 0};
+            if (rb + k < r1 && vi < nvec) q[k].v = psi[vi];
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const uint64_t rowbase = (rb + k) * 64 * E;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const double pr = prob<T>(q[k], e);
+                pP += pr;
+                const uint64_t ub = rowbase + e;
+#pragma unroll
+                for (int t = 0; t < kTB; ++t)
+                    if (t < nterms && (__popcll(ub & zm[t]) & 1)) pS[t] += pr;
+            }
+        }
+        neum_add(P, pP);
+#pragma unroll
+        for (int t = 0; t < kTB; ++t) neum_add(S[t], pS[t]);
+    }
+    // per-lane signed sums, then wave and block reduction in a fixed order
+    __shared__ double red[4][kTB + 1][2];
+    const int wv = threadIdx.x >> 6;
+    DD Pw = wave_reduce_dd(P, lane);
+    if (lane == 0) {
+        red[wv][kTB][0] = Pw.s;
+        red[wv][kTB][1] = Pw.c;
+    }
+#pragma unroll
+    for (int t = 0; t < kTB; ++t) {
+        if (t >= nterms) break;
+        const DD twoS{2.0 * S[t].s, 2.0 * S[t].c};
+        DD v = ((lanebits >> t) & 1) ? dd_add(twoS, DD{-P.s, -P.c}) : dd_add(P, DD{-twoS.s, -twoS.c});
+        v = wave_reduce_dd(v, lane);
+        if (lane == 0) {
+            red[wv][t][0] = v.s;
+            red[wv][t][1] = v.c;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x <= kTB) {
+        const int t = threadIdx.x;
+        if (t < nterms || t == kTB) {
+            DD acc = DD{red[0][t][0], red[0][t][1]};
+            for (int k = 1; k < 4; ++k) acc = dd_add(acc, DD{red[k][t][0], red[k][t][1]});
+            part[(blockIdx.x * (kTB + 1) + t) * 2] = acc.s;
+            part[(blockIdx.x * (kTB + 1) + t) * 2 + 1] = acc.c;
+        }
+    }
+}
+
+// Final fixed-order sum of nred partials for slots [first, first+count)
+// (one workgroup, one wavefront per slot); out[t - first] receives slot t.
+__global__ __launch_bounds__(256) void k_red_final(const double *__restrict__ part, uint64_t nred, int first, int count,
+                                                   double *__restrict__ out) {
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int t = first + wv; t < first + count; t += 4) {
+        DD acc = dd_zero();
+        for (uint64_t b = lane; b < nred; b += 64)
+            acc = dd_add(acc, DD{part[(b * (kTB + 1) + t) * 2], part[(b * (kTB + 1) + t) * 2 + 1]});
+        acc = wave_reduce_dd(acc, lane);
+        if (lane == 0) out[t - first] = dd_value(acc);
+    }
+}
+
+// ---- one general Pauli term -------------------------------------------
+// Units: segments of 64*E amplitudes. If x has bits at or above the segment
+// size, a unit is the pair (A, A ^ xh) with the lowest bit of xh zero in A;
+// otherwise a unit is one segment. Lanes get partner values with ds_bpermute.
+template <typename T>
+__global__ __launch_bounds__(256) void k_expect_xz(const u4 *__restrict__ psi, int n, uint64_t xmask, uint64_t zmask,
+                                                   uint64_t nred, double *__restrict__ part) {
+    constexpr int E = Amp<T>::E, LGE = Amp<T>::LGE, LB = 6 + LGE;
+    const int lane = threadIdx.x & 63;
+    const uint64_t N = 1ull << n;
+    const uint64_t lowmask = (1ull << LB) - 1;
+    const uint64_t xh = xmask & ~lowmask;
+    const uint32_t xl = (uint32_t)(xmask & lowmask);
+    const int hb = xh ? __ffsll((long long)xh) - 1 : 0;
+    const int nhb = xh ? 1 : 0;
+    const int hbits = n > LB ? n - LB : 0;
+    const uint64_t nunits = 1ull << (hbits - nhb);
+    const uint32_t nlow_valid = (uint32_t)std::min<uint64_t>(N, 1ull << LB);
+    const bool lane_valid = (uint32_t)(lane * E) < nlow_valid;
+    const uint64_t nwaves = nred * 4;
+    const uint64_t w = wave_id_global();
+    const uint64_t per = (nunits + nwaves - 1) / nwaves;
+    const uint64_t u0 = w * per, u1 = std::min<uint64_t>(nunits, u0 + per);
+    const int ny = __popcll(xmask & zmask) & 3;
+    DD accr = dd_zero(), acci = dd_zero();
+    const int lx = (int)(xl >> LGE);
+    const int rx = (int)(xl & (E - 1));
+    for (uint64_t u = u0; u < u1; ++u) {
+        const uint64_t baseA = deposit(u, &hb, nhb, LB);
+        const int nseg = xh ? 2 : 1;
+        Q seg[2];
+        uint64_t sbase[2] = {baseA, baseA ^ xh};
+        for (int s = 0; s < nseg; ++s) {
+            seg[s].v = u4{0, 0, 0, 0};
+            if (lane_valid) seg[s].v = psi[(sbase[s] >> LGE) + lane];
+        }
+        double pr = 0.0, pi = 0.0;
+        for (int s = 0; s < nseg; ++s) {
+            const Q &src = seg[xh ? (s ^ 1) : s];
+            const Q partner = lx ? lane_xor(src, lane, lx) : src;
+            if (!lane_valid) continue;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const uint64_t b = sbase[s] + (uint64_t)lane * E + e;
+                const Cx<T> ab = Amp<T>::get(seg[s], e);
+                const Cx<T> ax = Amp<T>::get(partner, e ^ rx);
+                // conj(ax) * ab
+                double re = (double)ax.re * (double)ab.re + (double)ax.im * (double)ab.im;
+                double im = (double)ax.re * (double)ab.im - (double)ax.im * (double)ab.re;
+                if (__popcll(b & zmask) & 1) {
+                    re = -re;
+                    im = -im;
+                }
+                pr += re;
+                pi += im;
+            }
+        }
+        // multiply by i^ny
+        double tr = pr, ti = pi;
+        if (ny == 1) {
+            tr = -pi;
+            ti = pr;
+        } else if (ny == 2) {
+            tr = -pr;
+            ti = -pi;
+        } else if (ny == 3) {
+            tr = pi;
+            ti = -pr;
+        }
+        neum_add(accr, tr);
+        neum_add(acci, ti);
+    }
+    __shared__ double red[4][2][2];
+    const int wv = threadIdx.x >> 6;
+    DD a = wave_reduce_dd(accr, lane), b = wave_reduce_dd(acci, lane);
+    if (lane == 0) {
+        red[wv][0][0] = a.s;
+        red[wv][0][1] = a.c;
+        red[wv][1][0] = b.s;
+        red[wv][1][1] = b.c;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        const int t = threadIdx.x;
+        DD acc{red[0][t][0], red[0][t][1]};
+        for (int k = 1; k < 4; ++k) acc = dd_add(acc, DD{red[k][t][0], red[k][t][1]});
+        part[(blockIdx.x * (kTB + 1) + t) * 2] = acc.s;
+        part[(blockIdx.x * (kTB + 1) + t) * 2 + 1] = acc.c;
+    }
+}
+
+inline double *wsd(void *ws) { return reinterpret_cast<double *>(ws); }
+inline const double *wsd(const void *ws) { return reinterpret_cast<const double *>(ws); }
+
+}  // namespace
+
+namespace svk {
+
+uint64_t measure_workspace_bytes(int n) { return ws_doubles(n) * sizeof(double) + 64 * sizeof(uint64_t); }
+
+const double *norm2_dev_ptr(const void *ws, int n) { return wsd(ws) + ws_layout(n).off_res; }
+
+hipError_t launch_cdf(const void *psi, int n, int is_c64, void *ws, hipStream_t s) {
+    const WS w = ws_layout(n);
+    double *d = wsd(ws);
+    const unsigned lblocks = (unsigned)((w.nleaf + 3) / 4);
+    if (is_c64)
+        hipLaunchKernelGGL(k_leafsum<float>, dim3(lblocks), dim3(256), 0, s, (const u4 *)psi, n, d + w.off_leafsum);
+    else
+        hipLaunchKernelGGL(k_leafsum<double>, dim3(lblocks), dim3(256), 0, s, (const u4 *)psi, n, d + w.off_leafsum);
+    hipLaunchKernelGGL(k_chunk_total, dim3((unsigned)w.nchunk), dim3(kScanThreads), 0, s, d + w.off_leafsum, w.nleaf,
+                       d + w.off_chunk);
+    hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kScanThreads), 0, s, d + w.off_chunk, w.nchunk, d + w.off_chunkpre,
+                       d + w.off_res);
+    hipLaunchKernelGGL(k_leaf_scan, dim3((unsigned)w.nchunk), dim3(kScanThreads), 0, s, d + w.off_leafsum, w.nleaf,
+                       d + w.off_chunkpre, d + w.off_res, d + w.off_leafcdf);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm(const void *psi, int n, int is_c64, void *ws, hipStream_t s) {
+    const WS w = ws_layout(n);
+    double *d = wsd(ws);
+    if (is_c64)
+        hipLaunchKernelGGL(k_zbatch<float>, dim3((unsigned)w.nred), dim3(256), 0, s, (const u4 *)psi, n,
+                           (const uint64_t *)nullptr, 0, w.nred, d + w.off_part);
+    else
+        hipLaunchKernelGGL(k_zbatch<double>, dim3((unsigned)w.nred), dim3(256), 0, s, (const u4 *)psi, n,
+                           (const uint64_t *)nullptr, 0, w.nred, d + w.off_part);
+    // the squared norm is slot kTB of the partials
+    hipLaunchKernelGGL(k_red_final, dim3(1), dim3(256), 0, s, d + w.off_part, w.nred, kTB, 1, d + w.off_res);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample(const void *psi, int n, int is_c64, const void *ws, int64_t shots, uint64_t seed,
+                         uint64_t s0, uint64_t *out_dev, hipStream_t s) {
+    if (shots <= 0) return hipSuccess;
+    const WS w = ws_layout(n);
+    const double *d = wsd(ws);
+    const unsigned blocks = (unsigned)((shots + 3) / 4);
+    if (is_c64)
+        hipLaunchKernelGGL(k_sample<float>, dim3(blocks), dim3(256), 0, s, (const u4 *)psi, n, d + w.off_leafcdf, shots,
+                           seed, s0, out_dev);
+    else
+        hipLaunchKernelGGL(k_sample<double>, dim3(blocks), dim3(256), 0, s, (const u4 *)psi, n, d + w.off_leafcdf,
+                           shots, seed, s0, out_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_expect_z(const void *psi, int n, int is_c64, const uint64_t *zmasks, int nterms, void *ws,
+                           double *out_dev, hipStream_t s) {
+    const WS w = ws_layout(n);
+    double *d = wsd(ws);
+    if (nterms > kTB) return hipErrorInvalidValue;
+    if (is_c64)
+        hipLaunchKernelGGL(k_zbatch<float>, dim3((unsigned)w.nred), dim3(256), 0, s, (const u4 *)psi, n, zmasks, nterms,
+                           w.nred, d + w.off_part);
+    else
+        hipLaunchKernelGGL(k_zbatch<double>, dim3((unsigned)w.nred), dim3(256), 0, s, (const u4 *)psi, n, zmasks,
+                           nterms, w.nred, d + w.off_part);
+    if (nterms > 0)
+        hipLaunchKernelGGL(k_red_final, dim3(1), dim3(256), 0, s, d + w.off_part, w.nred, 0, nterms, out_dev);
+    hipLaunchKernelGGL(k_red_final, dim3(1), dim3(256), 0, s, d + w.off_part, w.nred, kTB, 1, out_dev + nterms);
+    return hipGetLastError();
+}
+
+hipError_t launch_expect_xz(const void *psi, int n, int is_c64, uint64_t xmask, uint64_t zmask, void *ws,
+                            double *out_dev, hipStream_t s) {
+    const WS w = ws_layout(n);
+    double *d = wsd(ws);
+    if (is_c64)
+        hipLaunchKernelGGL(k_expect_xz<float>, dim3((unsigned)w.nred), dim3(256), 0, s, (const u4 *)psi, n, xmask, zmask,
+                           w.nred, d + w.off_part);
+    else
+        hipLaunchKernelGGL(k_expect_xz<double>, dim3((unsigned)w.nred), dim3(256), 0, s, (const u4 *)psi, n, xmask,
+                           zmask, w.nred, d + w.off_part);
+    hipLaunchKernelGGL(k_red_final, dim3(1), dim3(256), 0, s, d + w.off_part, w.nred, 0, 2, out_dev);
+    return hipGetLastError();
+}
+
+}  // namespace svk

@@ -1,0 +1,149 @@
+// sv_host.h -- host runtime internals of the state-vector library.
+#pragma once
+
+#include "../../include/sv.h"
+#include "sv_kernels.h"
+
+#include <hip/hip_runtime_api.h>
+
+#include <complex>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+namespace svh {
+
+typedef std::complex<double> cd;
+
+// ---- errors ---------------------------------------------------------------
+sv_status fail(sv_status st, const std::string &msg);
+sv_status hip_fail(hipError_t e, const char *what);
+#define SV_HIP(call)                                 \
+    do {                                             \
+        hipError_t _e = (call);                      \
+        if (_e != hipSuccess) return svh::hip_fail(_e, #call); \
+    } while (0)
+
+// ---- arena: first-fit sub-allocator over one device block -------------------
+class Arena {
+  public:
+    void init(char *base, uint64_t size);
+    // returns nullptr when no extent fits
+    void *alloc(uint64_t bytes, uint64_t align = 256);
+    void free(void *p);
+    uint64_t free_bytes() const;
+    uint64_t largest_free() const;
+    uint64_t size() const { return size_; }
+    bool contains(const void *p) const;
+
+  private:
+    mutable std::mutex mu_;
+    char *base_ = nullptr;
+    uint64_t size_ = 0;
+    std::map<uint64_t, uint64_t> free_;   // offset -> length
+    std::map<uint64_t, uint64_t> used_;   // offset -> length
+};
+
+// ---- tracing ----------------------------------------------------------------
+struct TraceAgg {
+    uint64_t launches = 0;
+    double seconds = 0, bytes = 0;
+};
+
+struct Tracer {
+    std::mutex mu;
+    bool on = false;
+    struct Pending {
+        std::string name;
+        hipEvent_t a, b;
+        double bytes;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    std::map<std::string, TraceAgg> agg;
+    hipEvent_t get_event();
+};
+
+// Brackets one launch with events when tracing is on.
+struct TraceScope {
+    Tracer *t;
+    hipStream_t s;
+    const char *name;
+    double bytes;
+    hipEvent_t a = nullptr, b = nullptr;
+    TraceScope(Tracer *tr, hipStream_t st, const char *nm, double by);
+    ~TraceScope();
+};
+
+// ---- parameter ring for large kernel argument blocks --------------------------
+struct ParamRing {
+    int nslots = 0;
+    uint64_t slot_bytes = 0;
+    char *dev = nullptr;     // device
+    char *host = nullptr;    // pinned host
+    std::vector<hipEvent_t> ev;
+    std::vector<bool> used;
+    int next = 0;
+    std::mutex mu;
+    sv_status init(int slots, uint64_t bytes);
+    void destroy();
+    // returns slot index after waiting for its previous use to finish
+    int acquire();
+    void release_after(int slot, hipStream_t s);
+};
+
+}  // namespace svh
+
+struct sv_ctx_s {
+    int device = 0;
+    svh::Arena arena;
+    char *arena_base = nullptr;
+    bool own_arena = false;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int renorm_period = 0;
+    svh::Tracer tracer;
+    svh::ParamRing ring;
+    int nstates = 0;
+    std::mutex mu;
+};
+
+struct sv_state_s {
+    sv_ctx ctx = nullptr;
+    int n = 0;
+    sv_dtype dtype = SV_C128;
+    void *psi = nullptr;
+    uint64_t bytes = 0;
+    void *ws = nullptr;         // measurement workspace (device)
+    uint64_t ws_bytes = 0;
+    hipStream_t stream = nullptr;
+    int gates_since_renorm = 0;
+    bool is_c64() const { return dtype == SV_C64; }
+};
+
+namespace svh {
+
+// gate matrices (Qiskit conventions), k <= 2 targets, controls first in q[]
+bool gate_matrix(int kind, const double *p, bool adjoint, cd *U, int *k, int *nc);
+int gate_nqubits(int kind);
+
+// apply one matrix gate on a state (classification + launch)
+sv_status apply_matrix(sv_state st, const cd *U, int k, const int *targets, const int *controls, int nc);
+// dense block via the fused kernels
+sv_status apply_fused(sv_state st, const cd *U, int k, const int *targets);
+
+// fusion planning
+struct Block {
+    std::vector<int> ops;       // indices into the op list, in application order
+    std::vector<int> qubits;    // block targets (sorted ascending)
+};
+std::vector<Block> plan_fusion(const sv_op *ops, int nops, int fuse_k);
+// U of a block on its qubits (bit j of the index <-> qubits[j])
+void block_matrix(const sv_op *ops, const Block &b, std::vector<cd> &U);
+
+// measurement drivers
+sv_status norm_device(sv_state st);   // leaves ||psi||^2 at norm2_dev_ptr
+uint64_t state_bytes(int n, sv_dtype dt);
+
+}  // namespace svh

@@ -1,0 +1,76 @@
+// sv_kernels.h -- launch interface between the host runtime and the gfx950
+// kernels of the state-vector library. Host-only declarations; no device code.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+namespace svk {
+
+// Amplitude index bits below LB(dtype) address amplitudes inside one
+// wavefront "segment": 64 lanes x 16 bytes = 1 KiB of contiguous state, i.e.
+// 64 complex128 (one per lane) or 128 complex64 (two per lane). Bits at or
+// above LB select the segment.
+inline int low_bits(int is_c64) { return is_c64 ? 7 : 6; }
+
+// A gate update in "group" form. Each group is a set of 2^K amplitudes whose
+// indices agree with `fv` on the bits of `fm` up to the flip vectors F_j: member
+// m of a group sits at base ^ (XOR of F_j over the set bits j of m), where base
+// has the bits of fm equal to fv. The members are multiplied by the 2^K x 2^K
+// matrix U (K = 0 gives a phase on the subspace {i : (i & fm) == fv}).
+struct GroupGate {
+    uint64_t fm = 0, fv = 0;
+    int K = 0;
+    uint64_t F[2] = {0, 0};
+    double U[2 * 16] = {0};   // row-major complex128, 2^K x 2^K
+};
+
+// A diagonal gate: every amplitude i whose control bits are all 1 is
+// multiplied by d[m], m = the target bits of i (bit j of m <- targets[j]).
+struct DiagGate {
+    uint64_t cmask = 0;
+    int k = 0;
+    int targets[8] = {0};
+    double d[2 * 32] = {0};   // 2^k complex128
+};
+
+struct TraceHook;  // per-launch event bracketing (optional)
+
+hipError_t launch_init(void *psi, int n, int is_c64, uint64_t basis, hipStream_t s);
+hipError_t launch_group(const GroupGate &g, void *psi, int n, int is_c64, hipStream_t s);
+hipError_t launch_diag(const DiagGate &g, void *psi, int n, int is_c64, hipStream_t s);
+// psi <- psi * rsqrt(*norm2_dev)
+hipError_t launch_scale_by_norm(void *psi, int n, int is_c64, const double *norm2_dev,
+                                hipStream_t s);
+
+// Dense k-qubit block (k <= 5) on arbitrary targets; U row-major complex128.
+// The kernel argument block (fused_args_bytes) is written to args_host (pinned)
+// and copied to args_dev on stream s; both must stay untouched until the
+// launch has run.
+uint64_t fused_args_bytes();
+hipError_t launch_fused_staged(const double *U, int k, const int *targets, void *psi, int n,
+                               int is_c64, hipStream_t s, int use_mfma, void *args_dev,
+                               void *args_host);
+
+// ---- measurement (FP64, compensated) -----------------------------------
+// Workspace needs (bytes) for a state of n qubits.
+uint64_t measure_workspace_bytes(int n);
+// Leaf sums, their exclusive scan (the leaf CDF) and the total: writes
+// leafcdf[0..nleaf] (nleaf+1 doubles) and total into ws. Returns via device.
+hipError_t launch_cdf(const void *psi, int n, int is_c64, void *ws, hipStream_t s);
+// After launch_cdf: total squared norm is at norm2_dev_ptr(ws, n).
+const double *norm2_dev_ptr(const void *ws, int n);
+hipError_t launch_norm(const void *psi, int n, int is_c64, void *ws, hipStream_t s);
+// Shots s0 .. s0+shots-1 (the counter of the generator), results to out_dev[0..shots).
+hipError_t launch_sample(const void *psi, int n, int is_c64, const void *ws, int64_t shots,
+                         uint64_t seed, uint64_t s0, uint64_t *out_dev, hipStream_t s);
+// Z-only Pauli batch (nterms <= 64): out_dev[t] = sum_i (-1)^{popc(i & z_t)} |psi_i|^2
+// (unnormalised) for t < nterms, out_dev[nterms] = sum_i |psi_i|^2.
+hipError_t launch_expect_z(const void *psi, int n, int is_c64, const uint64_t *zmasks,
+                           int nterms, void *ws, double *out_dev, hipStream_t s);
+// One general Pauli term: out_dev[0..1] = (re, im) of
+// sum_b conj(psi_{b^x}) psi_b i^{popc(x&z)} (-1)^{popc(b&z)} (unnormalised).
+hipError_t launch_expect_xz(const void *psi, int n, int is_c64, uint64_t xmask, uint64_t zmask,
+                            void *ws, double *out_dev, hipStream_t s);
+
+}  // namespace svk

@@ -1,0 +1,110 @@
+"""CPU tests of the C-ABI library: it loads, exports every declared symbol, its
+structs match the header's layout, and its host-only logic (gate matrices,
+fusion planning, argument checks) agrees with the oracle's definitions. No
+kernel is launched."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sv.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:sv_status|const char \*)\s*(sv_\w+)\s*\(", text, re.M)))
+
+
+def test_every_declared_symbol_is_exported(S):
+    names = declared_functions()
+    assert len(names) >= 25
+    L = S.load()
+    for n in names:
+        assert hasattr(L, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", S._abi.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (sv_\w+)", out))
+    assert set(names) <= exported
+    # every binding prototype names a declared function
+    assert set(S._abi.PROTOTYPES) == set(names)
+
+
+STRUCTS = {
+    "sv_ctx_opts": ["device", "arena", "arena_bytes", "stream", "renorm_period"],
+    "sv_op": ["kind", "flags", "q", "pad", "p"],
+    "sv_pauli": ["xmask", "zmask", "coeff"],
+    "sv_trace_rec": ["name", "launches", "seconds", "bytes"],
+    "sv_server_opts": ["arena_bytes", "max_active", "small_qubits", "max_queue", "nstreams"],
+    "sv_circuit": ["n", "dtype", "ops", "nops", "fuse_k", "shots", "seed", "terms", "nterms", "pad"],
+    "sv_result": ["samples", "expect", "weighted", "norm", "status", "pad", "t_submit_ns", "t_admit_ns",
+                  "t_done_ns"],
+    "sv_server_stats": ["submitted", "admitted", "completed", "rejected", "cancelled", "packed_launches",
+                        "packed_circuits", "queued", "active", "peak_bytes"],
+}
+
+
+def test_struct_layouts_match_header(S, tmp_path):
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sv.h"', "int main(void){"]
+    for st, fields in STRUCTS.items():
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (st, st))
+        for f in fields:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (st, f, st, f))
+    lines.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I" + os.path.dirname(HEADER), str(src), "-o", str(exe)])
+    got = dict(l.split() for l in subprocess.check_output([str(exe)], text=True).splitlines())
+    for st, fields in STRUCTS.items():
+        cls = getattr(S._abi, st)
+        assert ctypes.sizeof(cls) == int(got[st]), st
+        for f in fields:
+            assert getattr(cls, f).offset == int(got["%s.%s" % (st, f)]), (st, f)
+
+
+def test_gate_kind_order_matches_header(S):
+    text = open(HEADER).read()
+    body = re.search(r"typedef enum \{\s*(SV_GATE_H.*?)\} sv_gate_kind;", text, re.S).group(1)
+    names = [m.lower() for m in re.findall(r"SV_GATE_(\w+)", body) if m != "COUNT"]
+    assert names == S.GATE_KINDS
+
+
+@pytest.mark.parametrize("name", W.GATES_1Q + W.GATES_2Q + W.GATES_3Q)
+def test_library_gate_matrices_equal_oracle(S, O, name):
+    rng = np.random.default_rng(abs(hash(name)) % 1000)
+    for _ in range(4):
+        params = tuple(rng.uniform(0, 2 * np.pi, W.circuits.N_PARAMS.get(name, 0)))
+        U, k, nc = S.sv_gate_matrix(name, params)
+        Uo, ko, nco = O.gate_matrix(name, params)
+        assert (k, nc) == (ko, nco)
+        assert np.max(np.abs(U - Uo)) <= 1e-15
+        Ua, _, _ = S.sv_gate_matrix(name, params, adjoint=True)
+        assert np.max(np.abs(Ua - Uo.conj().T)) <= 1e-15
+
+
+def test_fusion_plan_counts(S):
+    ops = W.brickwork(12, 4, seed=1)
+    nb5, ns5 = S.sv_plan_fusion(ops, 12, 5)
+    nb2, _ = S.sv_plan_fusion(ops, 12, 2)
+    assert nb5 < nb2 < len(ops)
+    # a circuit acting on 5 qubits fuses into one block
+    ops = W.random_circuit(5, 50, seed=2, names=list(W.GATES_1Q) + list(W.GATES_2Q))
+    assert S.sv_plan_fusion(ops, 5, 5) == (1, 0)
+
+
+def test_fusion_rejects_bad_arguments(S):
+    with pytest.raises(S.SvError):
+        S.sv_plan_fusion([("h", (0,), ())], 4, 6)
+    with pytest.raises(S.SvError):
+        S.sv_plan_fusion([("h", (7,), ())], 4, 5)
+
+
+def test_unknown_gate_kind_is_invalid(S):
+    with pytest.raises(S.SvError) as e:
+        S.sv_gate_matrix(99)
+    assert e.value.status == S._abi.SV_E_INVALID

@@ -1,0 +1,61 @@
+"""GPU parity of dense k-qubit blocks (MFMA for states of >= k+4 qubits, the
+per-column kernel below that) and of fused gate-list runs, against the oracle."""
+import numpy as np
+import pytest
+
+import workloads as W
+from conftest import infidelity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [5, 8, 9, 10, 13, 16])
+def test_apply_fused_random_blocks(ctx, S, O, n, dtype):
+    rng = np.random.default_rng(7 * n)
+    with S.State(ctx, n, dtype) as st:
+        for k in range(1, min(5, n) + 1):
+            for trial in range(6):
+                t = list(rng.choice(n, size=k, replace=False))
+                if trial == 0:
+                    t = list(range(k))                    # lowest bits
+                elif trial == 1:
+                    t = list(range(n - k, n))[::-1]       # highest bits, reversed
+                U = W.random_unitary(k, int(rng.integers(1 << 30)))
+                psi0 = W.random_state(n, int(rng.integers(1 << 30)))
+                if dtype == "c64":
+                    psi0 = psi0.astype(np.complex64).astype(np.complex128)
+                want = O.apply_matrix(psi0.copy(), U, t)
+                st.copy_in(psi0)
+                st.apply_fused(U, t)
+                got = st.copy_out()
+                if dtype == "c128":
+                    assert np.max(np.abs(got - want)) <= 1e-13, (k, t)
+                else:
+                    assert infidelity(got, want) <= 1e-10, (k, t)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("fuse_k", [2, 3, 4, 5])
+def test_fused_runs_match_oracle(ctx, S, O, fuse_k, dtype):
+    for n, ops in [(14, W.brickwork(14, 8, seed=3)), (12, W.random_circuit(12, 300, seed=4)),
+                   (10, W.qft(10)), (7, W.random_circuit(7, 100, seed=5))]:
+        want = O.run(ops, n)
+        with S.State(ctx, n, dtype) as st:
+            st.run(ops, fuse_k=fuse_k)
+            got = st.copy_out()
+        if dtype == "c128":
+            assert np.max(np.abs(got - want)) <= 1e-12, (n, fuse_k)
+        else:
+            assert infidelity(got, want) <= 1e-5, (n, fuse_k)
+
+
+def test_fused_and_unfused_mirror(ctx, S):
+    n = 20
+    ops = W.brickwork(n, 10, seed=9)
+    inv = [(o[0], o[1], o[2], True) for o in reversed(ops)]
+    with S.State(ctx, n, "c128") as st:
+        st.run(ops, fuse_k=5)
+        st.run(inv, fuse_k=0)
+        psi = st.copy_out()
+    assert 1.0 - abs(psi[0]) ** 2 <= 1e-12

@@ -1,0 +1,96 @@
+"""GPU parity of the FP64 measurement path: squared norm, renormalisation,
+shot sampling (coupled to the oracle's sampler through the shared counter-based
+generator) and Pauli expectation values."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [1, 3, 9, 10, 11, 17])
+def test_norm_and_renormalize(ctx, S, O, n, dtype):
+    psi = W.random_state(n, n) * 1.7
+    with S.State(ctx, n, dtype) as st:
+        st.copy_in(psi)
+        src = psi.astype(np.complex64).astype(np.complex128) if dtype == "c64" else psi
+        want = O.norm2(np.ascontiguousarray(src))
+        assert abs(st.norm2() - want) <= 1e-14 * want
+        st.renormalize()
+        assert abs(st.norm2() - 1.0) <= (1e-14 if dtype == "c128" else 1e-6)
+
+
+def _mismatch_bound(F_a, F_b, shots):
+    w1 = float(np.sum(np.abs(F_a - F_b)) / F_a[-1])
+    return w1 * shots + 5 * math.sqrt(max(w1, 1e-300) * shots) + 1
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [1, 4, 10, 12, 16])
+def test_sampling_coupled_to_oracle(ctx, S, O, n, dtype):
+    shots, seed = 4096, 777 + n
+    ops = W.brickwork(n, 6, seed=n) if n > 1 else [("h", (0,), ())]
+    psi = O.run(ops, n)
+    with S.State(ctx, n, dtype) as st:
+        st.run(ops)
+        got = st.sample(shots, seed)
+        gstate = st.copy_out().astype(np.complex128)
+    want = O.sample(psi, shots, seed)
+    assert got.dtype == np.uint64 and got.shape == (shots,)
+    assert np.all(got < (1 << n))
+    mism = int(np.sum(got != want))
+    if dtype == "c128":
+        assert mism <= 1
+    else:
+        # same u per shot: a mismatch needs u between the two CDFs (W1 bound)
+        assert mism <= _mismatch_bound(O.cdf(gstate), O.cdf(psi), shots)
+
+
+def test_sampling_edge_cases(ctx, S, O):
+    with S.State(ctx, 12, "c128") as st:
+        st.reset(1234)
+        assert np.all(st.sample(1000, 5) == 1234)
+        assert st.sample(0, 5).shape == (0,)
+        st.reset(0)
+        st.run(W.ghz(12))
+        out = st.sample(20000, 6)
+        assert set(np.unique(out)) <= {0, 4095}
+        assert abs(int(np.sum(out == 0)) - 10000) <= 5 * math.sqrt(20000) / 2
+        # the shot counter continues across calls: shots 0..9 equal the first 10 of 20000
+        assert np.array_equal(st.sample(10, 6), out[:10])
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [2, 5, 10, 13])
+def test_expectations_match_oracle(ctx, S, O, n, dtype):
+    ops = W.random_circuit(n, 120, seed=50 + n)
+    psi = O.run(ops, n)
+    terms = W.random_paulis(n, 30, seed=n)
+    terms += [(0, z, 0.5) for z in np.random.default_rng(n).integers(0, 1 << n, 20)]   # > 16 Z-only terms
+    terms += [(0, 0, 1.0)]
+    with S.State(ctx, n, dtype) as st:
+        st.run(ops)
+        vals, wsum = st.expect(terms)
+    want = np.array([O.expect(psi, x, z).real for x, z, _ in terms])
+    tol = 1e-12 if dtype == "c128" else 2 * math.sqrt(1e-5)
+    assert np.max(np.abs(vals - want)) <= tol
+    assert abs(wsum - sum(c * w for (_, _, c), w in zip(terms, want))) <= tol * len(terms)
+
+
+def test_qaoa_energy_matches_oracle(ctx, S, O):
+    n = 14
+    ops, edges, terms = W.qaoa_maxcut(n, 3, seed=11)
+    psi = O.run(ops, n)
+    _, e_want = O.expect_terms(psi, terms)
+    with S.State(ctx, n, "c128") as st:
+        st.run(ops)
+        _, e128 = st.expect(terms)
+    with S.State(ctx, n, "c64") as st:
+        st.run(ops)
+        _, e64 = st.expect(terms)
+    assert abs(e128 - e_want) <= 1e-10
+    assert abs(e64 - e_want) <= 90 * math.sqrt(1e-5)

@@ -20,4 +20,7 @@ from .circuits import (  # noqa: F401
     serving_stream,
     poisson_arrivals,
     circuit_gate_count,
+    random_state,
+    random_unitary,
+    random_paulis,
 )

@@ -191,3 +191,32 @@ def random_circuit(n: int, ngates: int, seed: int, names=None):
         params = rng.uniform(0.0, TWO_PI, size=N_PARAMS.get(g, 0))
         ops.append(_op(g, qs, params))
     return ops
+
+
+def random_state(n: int, seed: int) -> np.ndarray:
+    """A seeded random complex128 vector of 2^n entries with unit 2-norm
+    (iid normal real and imaginary parts, then divided by the norm)."""
+    rng = np.random.default_rng(seed)
+    v = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    return (v / np.linalg.norm(v)).astype(np.complex128)
+
+
+def random_unitary(k: int, seed: int) -> np.ndarray:
+    """A seeded Haar-random 2^k x 2^k unitary (QR of a complex Gaussian
+    matrix with the phases of R's diagonal divided out)."""
+    rng = np.random.default_rng(seed)
+    K = 1 << k
+    A = rng.normal(size=(K, K)) + 1j * rng.normal(size=(K, K))
+    Q, R = np.linalg.qr(A)
+    return Q * (np.diag(R) / np.abs(np.diag(R)))
+
+
+def random_paulis(n: int, count: int, seed: int):
+    """Seeded random Pauli strings as (xmask, zmask, coeff) with coeff in [-1, 1]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        x = int(rng.integers(0, 1 << n))
+        z = int(rng.integers(0, 1 << n))
+        out.append((x, z, float(rng.uniform(-1, 1))))
+    return out
