@@ -58,7 +58,7 @@ __global__ __launch_bounds__(kBlock) void k_group(GArgs<T> a, u4 *__restrict__ p
     constexpr int E = A::E, LGE = A::LGE, LB = 6 + LGE;
     constexpr int NS = 1 << KH, NL = 1 << KL, M = 1 << (KH + KL);
     const int lane = threadIdx.x & 63;
-    const uint64_t wave = wave_id_global();
+    const uint64_t wave = wave_id_xcd();
 
     // Which member (if any) each of this lane's amplitudes is, per segment.
     int ml[E];
@@ -108,7 +108,16 @@ __global__ __launch_bounds__(kBlock) void k_group(GArgs<T> a, u4 *__restrict__ p
                     row[s][r][d] = Cx<T>{a.tab[2 * (s * M + d)], a.tab[2 * (s * M + d) + 1]};
     }
 
-    // Issue every load of this wavefront's slots before any arithmetic.
+    // Issue every load of this wavefront's slots before any arithmetic. Lanes
+    // holding no member of any group skip their loads (their amplitudes are
+    // neither changed nor needed as partners).
+    bool need[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        need[s] = false;
+#pragma unroll
+        for (int r = 0; r < E; ++r) need[s] = need[s] || mem[s][r];
+    }
     Q v[kSlots][NS];
     uint64_t vidx[kSlots][NS];
     bool act[kSlots];
@@ -121,7 +130,7 @@ __global__ __launch_bounds__(kBlock) void k_group(GArgs<T> a, u4 *__restrict__ p
         for (int s = 0; s < NS; ++s) {
             vidx[sl][s] = ((base ^ a.soff[s]) >> LGE) + lane;
             v[sl][s].v = u4{0, 0, 0, 0};
-            if (act[sl] && lane_valid) v[sl][s].v = psi[vidx[sl][s]];
+            if (act[sl] && lane_valid && need[s]) v[sl][s].v = ld_nt(psi + vidx[sl][s]);
         }
     }
 
@@ -170,12 +179,12 @@ __global__ __launch_bounds__(kBlock) void k_group(GArgs<T> a, u4 *__restrict__ p
                 A::set(out, r, acc);
             }
             if (E == 1 || all) {
-                if (any) psi[vidx[sl][s]] = out.v;
+                if (any) st_nt(psi + vidx[sl][s], out.v);
             } else if (any) {
                 // complex64: only one of the two amplitudes changed
                 uint64_t *p = reinterpret_cast<uint64_t *>(psi + vidx[sl][s]);
                 const int r = mem[s][0] ? 0 : 1;
-                p[r] = (uint64_t)out.w[2 * r] | ((uint64_t)out.w[2 * r + 1] << 32);
+                __builtin_nontemporal_store((uint64_t)out.w[2 * r] | ((uint64_t)out.w[2 * r + 1] << 32), p + r);
             }
         }
     }
@@ -202,8 +211,13 @@ __global__ __launch_bounds__(kBlock) void k_diag(DArgs<T> a, u4 *__restrict__ ps
     if (threadIdx.x < (2u << a.k)) sd[threadIdx.x] = a.d[threadIdx.x];
     __syncthreads();
     const int lane = threadIdx.x & 63;
-    const uint64_t wave = wave_id_global();
-    const bool lane_valid = (uint32_t)(lane * E) < a.nlow_valid;
+    const uint64_t wave = wave_id_xcd();
+    bool lane_valid = false;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const uint32_t j = lane * E + r;
+        lane_valid = lane_valid || (j < a.nlow_valid && (j & a.fm_low) == a.fv_low);
+    }
     Q v[kSlots];
     uint64_t vidx[kSlots], base[kSlots];
     bool act[kSlots];
@@ -214,7 +228,7 @@ __global__ __launch_bounds__(kBlock) void k_diag(DArgs<T> a, u4 *__restrict__ ps
         base[sl] = deposit(act[sl] ? outer : 0, a.hb, a.nhb, LB) | a.fv_high;
         vidx[sl] = (base[sl] >> LGE) + lane;
         v[sl].v = u4{0, 0, 0, 0};
-        if (act[sl] && lane_valid) v[sl].v = psi[vidx[sl]];
+        if (act[sl] && lane_valid) v[sl].v = ld_nt(psi + vidx[sl]);
     }
 #pragma unroll
     for (int sl = 0; sl < kSlots; ++sl) {
@@ -233,20 +247,23 @@ __global__ __launch_bounds__(kBlock) void k_diag(DArgs<T> a, u4 *__restrict__ ps
             A::set(out, r, cfma(acc, dm, A::get(v[sl], r)));
             any = true;
         }
-        if (any) psi[vidx[sl]] = out.v;
+        if (any) st_nt(psi + vidx[sl], out.v);
     }
 }
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_init(u4 *__restrict__ psi, uint64_t nvec, uint64_t basis) {
     using A = Amp<T>;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t bvec = basis >> A::LGE;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvec; i += stride) {
+    const uint64_t i0 = xcd_block() * (kBlock * kSlots) + threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < kSlots; ++u) {
+        const uint64_t i = i0 + u * kBlock;
+        if (i >= nvec) continue;
         Q q;
         q.v = u4{0, 0, 0, 0};
         if (i == bvec) A::set(q, (int)(basis & (A::E - 1)), Cx<T>{T(1), T(0)});
-        psi[i] = q.v;
+        st_nt(psi + i, q.v);
     }
 }
 
@@ -254,10 +271,13 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_scale(u4 *__restrict__ psi, uint64_t nvec,
                                                   const double *__restrict__ norm2) {
     const double sc = 1.0 / sqrt(*norm2);
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvec; i += stride) {
+    const uint64_t i0 = xcd_block() * (kBlock * kSlots) + threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < kSlots; ++u) {
+        const uint64_t i = i0 + u * kBlock;
+        if (i >= nvec) continue;
         Q q;
-        q.v = psi[i];
+        q.v = ld_nt(psi + i);
         if (sizeof(T) == 8) {
             q.d[0] *= sc;
             q.d[1] *= sc;
@@ -265,15 +285,14 @@ __global__ __launch_bounds__(kBlock) void k_scale(u4 *__restrict__ psi, uint64_t
 #pragma unroll
             for (int c = 0; c < 4; ++c) q.f[c] = (float)((double)q.f[c] * sc);
         }
-        psi[i] = q.v;
+        st_nt(psi + i, q.v);
     }
 }
 
 inline int popc64(uint64_t x) { return __builtin_popcountll(x); }
 
-uint64_t grid_stride_blocks(uint64_t nvec) {
-    uint64_t blocks = (nvec + kBlock - 1) / kBlock;
-    return std::min<uint64_t>(std::max<uint64_t>(blocks, 1), 256ull * 64);
+uint64_t oneshot_blocks(uint64_t nvec) {
+    return std::max<uint64_t>(1, (nvec + kBlock * kSlots - 1) / (kBlock * kSlots));
 }
 
 // Common planning of the outer enumeration: high fixed bits, counts.
@@ -402,7 +421,7 @@ namespace svk {
 
 hipError_t launch_init(void *psi, int n, int is_c64, uint64_t basis, hipStream_t s) {
     const uint64_t nvec = is_c64 ? ((1ull << n) + 1) / 2 : (1ull << n);
-    const uint64_t blocks = grid_stride_blocks(nvec);
+    const uint64_t blocks = oneshot_blocks(nvec);
     if (is_c64)
         hipLaunchKernelGGL(k_init<float>, dim3((unsigned)blocks), dim3(kBlock), 0, s, (u4 *)psi, nvec, basis);
     else
@@ -420,7 +439,7 @@ hipError_t launch_diag(const DiagGate &g, void *psi, int n, int is_c64, hipStrea
 
 hipError_t launch_scale_by_norm(void *psi, int n, int is_c64, const double *norm2_dev, hipStream_t s) {
     const uint64_t nvec = is_c64 ? ((1ull << n) + 1) / 2 : (1ull << n);
-    const uint64_t blocks = grid_stride_blocks(nvec);
+    const uint64_t blocks = oneshot_blocks(nvec);
     if (is_c64)
         hipLaunchKernelGGL(k_scale<float>, dim3((unsigned)blocks), dim3(kBlock), 0, s, (u4 *)psi, nvec, norm2_dev);
     else

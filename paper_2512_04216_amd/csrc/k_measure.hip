@@ -77,7 +77,7 @@ __device__ inline double prob(const Q &q, int r) {
 template <typename T>
 __global__ __launch_bounds__(256) void k_leafsum(const u4 *__restrict__ psi, int n, double *__restrict__ leafsum) {
     constexpr int E = Amp<T>::E;
-    const uint64_t leaf = wave_id_global();
+    const uint64_t leaf = wave_id_xcd();
     const uint64_t nleaf = nleaf_of(n);
     if (leaf >= nleaf) return;
     const int lane = threadIdx.x & 63;
@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void k_leafsum(const u4 *__restrict__ psi, int
     DD acc = dd_zero();
     for (uint64_t vi = lane; vi < nvec; vi += 64) {
         Q q;
-        q.v = p[vi];
+        q.v = ld_nt(p + vi);
 #pragma unroll
         for (int r = 0; r < E; ++r) neum_add(acc, prob<T>(q, r));
     }
@@ -318,7 +318,8 @@ __global__ __launch_bounds__(256) void k_zbatch(const u4 *__restrict__ psi, int 
     const uint64_t nvec = (1ull << n) >= (uint64_t)E ? (1ull << n) / E : 1ull;
     const uint64_t nrows = (nvec + 63) / 64;
     const uint64_t nwaves = nred * 4;
-    const uint64_t w = wave_id_global();
+    const uint64_t blk = xcd_block();
+    const uint64_t w = blk * 4 + (uint64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     uint64_t zm[kTB];
     uint32_t lanebits = 0;
 #pragma unroll
@@ -344,7 +345,7 @@ __global__ __launch_bounds__(256) void k_zbatch(const u4 *__restrict__ psi, int 
         for (int k = 0; k < CH; ++k) {
             const uint64_t vi = (rb + k) * 64 + lane;
             q[k].v = u4{0, 0, 0, 0};
-            if (rb + k < r1 && vi < nvec) q[k].v = psi[vi];
+            if (rb + k < r1 && vi < nvec) q[k].v = ld_nt(psi + vi);
         }
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
@@ -388,8 +389,8 @@ __global__ __launch_bounds__(256) void k_zbatch(const u4 *__restrict__ psi, int 
         if (t < nterms || t == kTB) {
             DD acc = DD{red[0][t][0], red[0][t][1]};
             for (int k = 1; k < 4; ++k) acc = dd_add(acc, DD{red[k][t][0], red[k][t][1]});
-            part[(blockIdx.x * (kTB + 1) + t) * 2] = acc.s;
-            part[(blockIdx.x * (kTB + 1) + t) * 2 + 1] = acc.c;
+            part[(blk * (kTB + 1) + t) * 2] = acc.s;
+            part[(blk * (kTB + 1) + t) * 2 + 1] = acc.c;
         }
     }
 }
@@ -428,7 +429,8 @@ __global__ __launch_bounds__(256) void k_expect_xz(const u4 *__restrict__ psi, i
     const uint32_t nlow_valid = (uint32_t)std::min<uint64_t>(N, 1ull << LB);
     const bool lane_valid = (uint32_t)(lane * E) < nlow_valid;
     const uint64_t nwaves = nred * 4;
-    const uint64_t w = wave_id_global();
+    const uint64_t blk = xcd_block();
+    const uint64_t w = blk * 4 + (uint64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t per = (nunits + nwaves - 1) / nwaves;
     const uint64_t u0 = w * per, u1 = std::min<uint64_t>(nunits, u0 + per);
     const int ny = __popcll(xmask & zmask) & 3;
@@ -442,7 +444,7 @@ __global__ __launch_bounds__(256) void k_expect_xz(const u4 *__restrict__ psi, i
         uint64_t sbase[2] = {baseA, baseA ^ xh};
         for (int s = 0; s < nseg; ++s) {
             seg[s].v = u4{0, 0, 0, 0};
-            if (lane_valid) seg[s].v = psi[(sbase[s] >> LGE) + lane];
+            if (lane_valid) seg[s].v = ld_nt(psi + (sbase[s] >> LGE) + lane);
         }
         double pr = 0.0, pi = 0.0;
         for (int s = 0; s < nseg; ++s) {
@@ -494,8 +496,8 @@ __global__ __launch_bounds__(256) void k_expect_xz(const u4 *__restrict__ psi, i
         const int t = threadIdx.x;
         DD acc{red[0][t][0], red[0][t][1]};
         for (int k = 1; k < 4; ++k) acc = dd_add(acc, DD{red[k][t][0], red[k][t][1]});
-        part[(blockIdx.x * (kTB + 1) + t) * 2] = acc.s;
-        part[(blockIdx.x * (kTB + 1) + t) * 2 + 1] = acc.c;
+        part[(blk * (kTB + 1) + t) * 2] = acc.s;
+        part[(blk * (kTB + 1) + t) * 2 + 1] = acc.c;
     }
 }
 

