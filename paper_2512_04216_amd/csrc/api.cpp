@@ -178,7 +178,7 @@ sv_status norm_device(sv_state st) {
     return SV_OK;
 }
 
-static sv_status renorm(sv_state st) {
+sv_status renorm(sv_state st) {
     sv_status r = norm_device(st);
     if (r) return r;
     TraceScope ts(&st->ctx->tracer, st->stream, "scale", 2.0 * st->bytes);
@@ -204,7 +204,7 @@ static sv_status check_qubits(sv_state st, const int *q, int cnt, uint64_t *mask
     return SV_OK;
 }
 
-static sv_status apply_op(sv_state st, const sv_op &o) {
+sv_status apply_op(sv_state st, const sv_op &o) {
     cd U[16];
     int k, nc;
     if (!gate_matrix(o.kind, o.p, (o.flags & SV_OP_ADJOINT) != 0, U, &k, &nc))
@@ -307,6 +307,12 @@ sv_status sv_ctx_free_bytes(sv_ctx c, uint64_t *total, uint64_t *largest) {
 
 sv_status sv_create(sv_ctx c, int n, sv_dtype dt, sv_state *out) {
     if (!c || !out) return fail(SV_E_INVALID, "null argument");
+    return svh::state_create(c, n, dt, c->stream, out);
+}
+
+}  // extern "C"
+
+sv_status svh::state_create(sv_ctx c, int n, sv_dtype dt, hipStream_t stream, sv_state *out) {
     if (dt != SV_C64 && dt != SV_C128) return fail(SV_E_INVALID, "dtype must be SV_C64 or SV_C128");
     const int nmax = dt == SV_C64 ? SV_MAX_QUBITS_C64 : SV_MAX_QUBITS_C128;
     if (n < 1 || n > nmax) return fail(SV_E_INVALID, "n out of range [1, " + std::to_string(nmax) + "]");
@@ -327,7 +333,7 @@ sv_status sv_create(sv_ctx c, int n, sv_dtype dt, sv_state *out) {
         delete st;
         return fail(SV_E_OOM, "arena cannot hold the measurement workspace");
     }
-    st->stream = c->stream;
+    st->stream = stream;
     {
         std::lock_guard<std::mutex> g(c->mu);
         c->nstates++;
@@ -341,9 +347,17 @@ sv_status sv_create(sv_ctx c, int n, sv_dtype dt, sv_state *out) {
     return SV_OK;
 }
 
+extern "C" {
+
 sv_status sv_destroy(sv_state st) {
     if (!st) return fail(SV_E_INVALID, "null state");
     hipStreamSynchronize(st->stream);
+    return svh::state_release(st);
+}
+
+}  // extern "C"
+
+sv_status svh::state_release(sv_state st) {
     st->ctx->arena.free(st->ws);
     st->ctx->arena.free(st->psi);
     {
@@ -353,6 +367,8 @@ sv_status sv_destroy(sv_state st) {
     delete st;
     return SV_OK;
 }
+
+extern "C" {
 
 sv_status sv_reset(sv_state st, uint64_t basis) {
     if (!st) return fail(SV_E_INVALID, "null state");

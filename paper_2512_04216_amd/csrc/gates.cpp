@@ -112,10 +112,9 @@ static const char *group_name(int K, uint64_t F0, uint64_t F1, int lb) {
     return nh == 2 ? "group_h2" : (nh == 1 ? "group_h1l1" : "group_l2");
 }
 
-sv_status apply_matrix(sv_state st, const cd *U, int k, const int *targets, const int *controls, int nc) {
+GateDesc classify(const cd *U, int k, const int *targets, const int *controls, int nc) {
     const int K = 1 << k;
-    const int s = st->is_c64() ? 8 : 16;
-    const int lb = svk::low_bits(st->is_c64());
+    GateDesc d;
     uint64_t cmask = 0, tmask = 0;
     for (int j = 0; j < nc; ++j) cmask |= 1ull << controls[j];
     for (int j = 0; j < k; ++j) tmask |= 1ull << targets[j];
@@ -126,7 +125,6 @@ sv_status apply_matrix(sv_state st, const cd *U, int k, const int *targets, cons
                 diag = false;
                 break;
             }
-    Tracer *tr = &st->ctx->tracer;
     if (diag) {
         int nonunit = 0, which = -1;
         for (int m = 0; m < K; ++m)
@@ -134,32 +132,31 @@ sv_status apply_matrix(sv_state st, const cd *U, int k, const int *targets, cons
                 ++nonunit;
                 which = m;
             }
-        if (nonunit == 0) return SV_OK;
+        if (nonunit == 0) {
+            d.kind = GateDesc::NOOP;
+            return d;
+        }
         if (nonunit == 1) {
-            svk::GroupGate g;
-            g.fm = cmask | tmask;
-            g.fv = cmask | qubit_bits(which, targets, k);
-            g.K = 0;
-            g.U[0] = U[which * K + which].real();
-            g.U[1] = U[which * K + which].imag();
-            TraceScope ts(tr, st->stream, "group_phase", group_bytes(st->n, s, 0, g.fm));
-            SV_HIP(svk::launch_group(g, st->psi, st->n, st->is_c64(), st->stream));
-            return SV_OK;
+            d.kind = GateDesc::GROUP;
+            d.group.fm = cmask | tmask;
+            d.group.fv = cmask | qubit_bits(which, targets, k);
+            d.group.K = 0;
+            d.group.U[0] = U[which * K + which].real();
+            d.group.U[1] = U[which * K + which].imag();
+            return d;
         }
-        svk::DiagGate g;
-        g.cmask = cmask;
-        g.k = k;
-        for (int j = 0; j < k; ++j) g.targets[j] = targets[j];
+        d.kind = GateDesc::DIAG;
+        d.diag.cmask = cmask;
+        d.diag.k = k;
+        for (int j = 0; j < k; ++j) d.diag.targets[j] = targets[j];
         for (int m = 0; m < K; ++m) {
-            g.d[2 * m] = U[m * K + m].real();
-            g.d[2 * m + 1] = U[m * K + m].imag();
+            d.diag.d[2 * m] = U[m * K + m].real();
+            d.diag.d[2 * m + 1] = U[m * K + m].imag();
         }
-        TraceScope ts(tr, st->stream, "diag", 2.0 * s * std::ldexp(1.0, st->n - __builtin_popcountll(cmask)));
-        SV_HIP(svk::launch_diag(g, st->psi, st->n, st->is_c64(), st->stream));
-        return SV_OK;
+        return d;
     }
     // two-level: identity outside two basis states
-    std::vector<int> active;
+    int active[32], na = 0;
     for (int m = 0; m < K; ++m) {
         bool ident = true;
         for (int q = 0; q < K; ++q) {
@@ -169,40 +166,64 @@ sv_status apply_matrix(sv_state st, const cd *U, int k, const int *targets, cons
                 break;
             }
         }
-        if (!ident) active.push_back(m);
+        if (!ident) active[na++] = m;
     }
-    if (active.size() == 2) {
+    if (na == 2) {
         const int p0 = active[0], p1 = active[1];
-        svk::GroupGate g;
-        g.fm = cmask | tmask;
-        g.fv = cmask | qubit_bits(p0, targets, k);
-        g.K = 1;
-        g.F[0] = qubit_bits(p0 ^ p1, targets, k);
+        d.kind = GateDesc::GROUP;
+        d.group.fm = cmask | tmask;
+        d.group.fv = cmask | qubit_bits(p0, targets, k);
+        d.group.K = 1;
+        d.group.F[0] = qubit_bits(p0 ^ p1, targets, k);
         const cd u2[4] = {U[p0 * K + p0], U[p0 * K + p1], U[p1 * K + p0], U[p1 * K + p1]};
         for (int i = 0; i < 4; ++i) {
-            g.U[2 * i] = u2[i].real();
-            g.U[2 * i + 1] = u2[i].imag();
+            d.group.U[2 * i] = u2[i].real();
+            d.group.U[2 * i + 1] = u2[i].imag();
         }
-        TraceScope ts(tr, st->stream, group_name(1, g.F[0], 0, lb), group_bytes(st->n, s, 1, g.fm));
-        SV_HIP(svk::launch_group(g, st->psi, st->n, st->is_c64(), st->stream));
-        return SV_OK;
+        return d;
     }
     if (k == 2) {
-        svk::GroupGate g;
-        g.fm = cmask | tmask;
-        g.fv = cmask;
-        g.K = 2;
-        g.F[0] = 1ull << targets[0];
-        g.F[1] = 1ull << targets[1];
+        d.kind = GateDesc::GROUP;
+        d.group.fm = cmask | tmask;
+        d.group.fv = cmask;
+        d.group.K = 2;
+        d.group.F[0] = 1ull << targets[0];
+        d.group.F[1] = 1ull << targets[1];
         for (int i = 0; i < 16; ++i) {
-            g.U[2 * i] = U[i].real();
-            g.U[2 * i + 1] = U[i].imag();
+            d.group.U[2 * i] = U[i].real();
+            d.group.U[2 * i + 1] = U[i].imag();
         }
-        TraceScope ts(tr, st->stream, group_name(2, g.F[0], g.F[1], lb), group_bytes(st->n, s, 2, g.fm));
+        return d;
+    }
+    d.kind = GateDesc::DENSE;
+    return d;
+}
+
+double desc_bytes(const GateDesc &d, int n, int s) {
+    if (d.kind == GateDesc::GROUP) return group_bytes(n, s, d.group.K, d.group.fm);
+    if (d.kind == GateDesc::DIAG) return 2.0 * s * std::ldexp(1.0, n - __builtin_popcountll(d.diag.cmask));
+    return 0.0;
+}
+
+sv_status apply_matrix(sv_state st, const cd *U, int k, const int *targets, const int *controls, int nc) {
+    const int K = 1 << k;
+    const int s = st->is_c64() ? 8 : 16;
+    const int lb = svk::low_bits(st->is_c64());
+    Tracer *tr = &st->ctx->tracer;
+    const GateDesc d = classify(U, k, targets, controls, nc);
+    if (d.kind == GateDesc::NOOP) return SV_OK;
+    if (d.kind == GateDesc::GROUP) {
+        const svk::GroupGate &g = d.group;
+        TraceScope ts(tr, st->stream, group_name(g.K, g.F[0], g.F[1], lb), desc_bytes(d, st->n, s));
         SV_HIP(svk::launch_group(g, st->psi, st->n, st->is_c64(), st->stream));
         return SV_OK;
     }
-    // dense k >= 3 (or a dense 1-qubit gate would have been two-level)
+    if (d.kind == GateDesc::DIAG) {
+        TraceScope ts(tr, st->stream, "diag", desc_bytes(d, st->n, s));
+        SV_HIP(svk::launch_diag(d.diag, st->psi, st->n, st->is_c64(), st->stream));
+        return SV_OK;
+    }
+    // dense k >= 3 (a dense 1-qubit gate is always two-level)
     if (nc == 0) return apply_fused(st, U, k, targets);
     // controlled dense block: embed the controls as extra targets
     const int kk = k + nc;

@@ -1,0 +1,228 @@
+// k_packed.hip -- one persistent launch for many small circuits (gfx950).
+//
+// Serving many small circuits one kernel per gate would be bound by launch
+// latency (the paper notes that GPU simulation can lose to CPUs on small or
+// batched workloads, Sec. II). Here each workgroup takes whole circuits: the
+// state lives in LDS (2^n amplitudes), every gate of the circuit is applied in
+// LDS with a barrier between gates, then the FP64 probabilities, their CDF, the
+// shots and the Pauli expectations are computed in the same workgroup and
+// written out. A circuit is always handled the same way by one workgroup, so
+// its results do not depend on which other circuits share the launch.
+#include "sv_device.h"
+#include "sv_kernels.h"
+
+#include <algorithm>
+
+using namespace svd;
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ inline uint32_t dep32(uint32_t c, uint32_t fixed) {
+    // insert zero bits at the set positions of `fixed` (ascending)
+    while (fixed) {
+        const int p = __ffs(fixed) - 1;
+        fixed &= fixed - 1;
+        c = ((c >> p) << (p + 1)) | (c & ((1u << p) - 1u));
+    }
+    return c;
+}
+
+__device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t s) {
+    uint64_t z = seed + (s + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+template <typename T>
+__device__ inline Cx<T> cmul(Cx<T> a, Cx<T> b) {
+    return Cx<T>{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+
+template <typename T>
+__device__ inline Cx<T> pool_at(const double *pool, uint32_t i) {
+    return Cx<T>{(T)pool[2 * i], (T)pool[2 * i + 1]};
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_packed(svk::PackedBatch b) {
+    extern __shared__ double lds_d[];
+    const int tid = threadIdx.x;
+    for (int ci = blockIdx.x; ci < b.ncirc; ci += gridDim.x) {
+        const svk::PCirc c = b.circ[ci];
+        const int n = c.n;
+        const uint32_t N = 1u << n;
+        const uint32_t nleaf = n > 6 ? (N >> 6) : 1u;
+        const uint32_t leaf_len = n > 6 ? 64u : N;
+        Cx<T> *psi = reinterpret_cast<Cx<T> *>(lds_d);
+        double *leafsum = lds_d + (size_t)(sizeof(Cx<T>) * b.max_amps + 7) / 8;
+        double *leafcdf = leafsum + b.max_leaves;
+        double *red = leafcdf + b.max_leaves + 1;   // 2 * kThreads doubles
+        // |0...0>
+        for (uint32_t i = tid; i < N; i += kThreads) psi[i] = Cx<T>{T(i == 0), T(0)};
+        __syncthreads();
+        for (int g = c.gate_begin; g < c.gate_end; ++g) {
+            const svk::PGate G = b.gates[g];
+            const uint32_t count = N >> __popc(G.fm);
+            if (G.type == svk::PGate::PHASE) {
+                const Cx<T> ph = pool_at<T>(b.pool, G.uoff);
+                for (uint32_t k = tid; k < count; k += kThreads) {
+                    const uint32_t i = dep32(k, G.fm) | G.fv;
+                    psi[i] = cmul(ph, psi[i]);
+                }
+            } else if (G.type == svk::PGate::PAIR) {
+                const Cx<T> u0 = pool_at<T>(b.pool, G.uoff), u1 = pool_at<T>(b.pool, G.uoff + 1),
+                            u2 = pool_at<T>(b.pool, G.uoff + 2), u3 = pool_at<T>(b.pool, G.uoff + 3);
+                for (uint32_t k = tid; k < count; k += kThreads) {
+                    const uint32_t i = dep32(k, G.fm) | G.fv, j = i ^ G.f0;
+                    const Cx<T> x = psi[i], y = psi[j];
+                    Cx<T> nx{0, 0}, ny{0, 0};
+                    nx = cfma(cfma(nx, u0, x), u1, y);
+                    ny = cfma(cfma(ny, u2, x), u3, y);
+                    psi[i] = nx;
+                    psi[j] = ny;
+                }
+            } else if (G.type == svk::PGate::QUAD) {
+                Cx<T> u[16];
+#pragma unroll
+                for (int e = 0; e < 16; ++e) u[e] = pool_at<T>(b.pool, G.uoff + e);
+                for (uint32_t k = tid; k < count; k += kThreads) {
+                    const uint32_t i0 = dep32(k, G.fm) | G.fv;
+                    const uint32_t idx[4] = {i0, i0 ^ G.f0, i0 ^ G.f1, i0 ^ G.f0 ^ G.f1};
+                    Cx<T> v[4];
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) v[m] = psi[idx[m]];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        Cx<T> acc{0, 0};
+#pragma unroll
+                        for (int m = 0; m < 4; ++m) acc = cfma(acc, u[r * 4 + m], v[m]);
+                        psi[idx[r]] = acc;
+                    }
+                }
+            } else {   // DIAG: f0 packs up to 4 target positions, one per byte
+                for (uint32_t k = tid; k < count; k += kThreads) {
+                    const uint32_t i = dep32(k, G.fm) | G.fv;
+                    uint32_t m = 0;
+                    for (int t = 0; t < (int)G.k; ++t) m |= ((i >> ((G.f0 >> (8 * t)) & 0xff)) & 1u) << t;
+                    psi[i] = cmul(pool_at<T>(b.pool, G.uoff + m), psi[i]);
+                }
+            }
+            __syncthreads();
+        }
+        // ---- probabilities: leaf sums (plain, in index order), then the leaf
+        // CDF with Neumaier summation by one thread
+        for (uint32_t l = tid; l < nleaf; l += kThreads) {
+            double s = 0.0;
+            for (uint32_t i = l * leaf_len; i < (l + 1) * leaf_len; ++i) {
+                const double re = (double)psi[i].re, im = (double)psi[i].im;
+                s += fma(re, re, im * im);
+            }
+            leafsum[l] = s;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            DD run = dd_zero();
+            for (uint32_t l = 0; l < nleaf; ++l) {
+                leafcdf[l] = dd_value(run);
+                neum_add(run, leafsum[l]);
+            }
+            leafcdf[nleaf] = dd_value(run);
+        }
+        __syncthreads();
+        const double total = leafcdf[nleaf];
+        if (tid == 0) b.res[c.res_off] = total;
+        // ---- shots
+        for (int64_t s = tid; s < c.shots; s += kThreads) {
+            const double u = (double)(splitmix64_at(c.seed, (uint64_t)s) >> 11) * 0x1.0p-53;
+            const double r = u * total;
+            uint32_t lo = 0, hi = nleaf;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (leafcdf[mid + 1] > r) hi = mid;
+                else lo = mid + 1;
+            }
+            const bool clamp = lo == nleaf;
+            if (clamp) {
+                uint32_t a = 0, e = nleaf - 1;
+                while (a < e) {
+                    const uint32_t mid = (a + e) >> 1;
+                    if (leafcdf[mid + 1] >= total) e = mid;
+                    else a = mid + 1;
+                }
+                lo = a;
+            }
+            double acc = leafcdf[lo];
+            int64_t found = -1, lastnz = -1;
+            for (uint32_t i = lo * leaf_len; i < (lo + 1) * leaf_len; ++i) {
+                const double re = (double)psi[i].re, im = (double)psi[i].im;
+                const double p = fma(re, re, im * im);
+                acc += p;
+                if (p > 0.0) lastnz = i;
+                if (!clamp && acc > r) {
+                    found = i;
+                    break;
+                }
+            }
+            if (found < 0) found = lastnz < 0 ? 0 : lastnz;
+            b.samples[c.sample_off + s] = (uint64_t)found;
+        }
+        // ---- expectations <P_t> / total
+        for (int t = c.term_begin; t < c.term_end; ++t) {
+            const uint32_t x = (uint32_t)b.tx[t], z = (uint32_t)b.tz[t];
+            const int ny = __popc(x & z) & 3;
+            DD ar = dd_zero(), ai = dd_zero();
+            for (uint32_t i = tid; i < N; i += kThreads) {
+                const Cx<T> a = psi[i], p = psi[i ^ x];
+                double re = (double)p.re * (double)a.re + (double)p.im * (double)a.im;
+                double im = (double)p.re * (double)a.im - (double)p.im * (double)a.re;
+                if (__popc(i & z) & 1) {
+                    re = -re;
+                    im = -im;
+                }
+                neum_add(ar, re);
+                neum_add(ai, im);
+            }
+            double vr = dd_value(ar), vi = dd_value(ai);
+            double tr = vr;
+            if (ny == 1) tr = -vi;
+            else if (ny == 2) tr = -vr;
+            else if (ny == 3) tr = vi;
+            red[tid] = tr;
+            __syncthreads();
+            if (tid == 0) {
+                DD acc = dd_zero();
+                for (int k = 0; k < kThreads; ++k) neum_add(acc, red[k]);
+                b.res[c.res_off + 1 + (t - c.term_begin)] = dd_value(acc) / total;
+            }
+            __syncthreads();
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+namespace svk {
+
+uint64_t packed_lds_bytes(int max_qubits, int is_c64) {
+    const uint64_t amps = 1ull << max_qubits;
+    const uint64_t leaves = max_qubits > 6 ? amps >> 6 : 1;
+    const uint64_t state = ((is_c64 ? 8 : 16) * amps + 7) / 8 * 8;
+    return state + 8 * (leaves + leaves + 1 + kThreads);
+}
+
+hipError_t launch_packed(const PackedBatch &b, int is_c64, int max_qubits, int max_blocks, hipStream_t s) {
+    if (b.ncirc <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)std::min(b.ncirc, std::max(1, max_blocks));
+    const size_t lds = (size_t)packed_lds_bytes(max_qubits, is_c64);
+    if (is_c64)
+        hipLaunchKernelGGL(k_packed<float>, dim3(blocks), dim3(kThreads), lds, s, b);
+    else
+        hipLaunchKernelGGL(k_packed<double>, dim3(blocks), dim3(kThreads), lds, s, b);
+    return hipGetLastError();
+}
+
+}  // namespace svk

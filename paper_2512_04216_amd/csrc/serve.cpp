@@ -1,12 +1,748 @@
-// serve.cpp -- placeholder until the serving loop lands.
+// serve.cpp -- continuous-batching request server over one GPU.
+//
+// The paper runs GPU backends from a single host thread (Sec. III-B) and sends
+// heterogeneous batches of circuits through one interface (Sec. IV-B). Here one
+// driver thread:
+//   * admits queued circuits in arrival order while their footprint fits: the
+//     2^n-amplitude state plus its measurement workspace and result buffers for
+//     a large circuit, a slot in the next packed launch for a small one. A
+//     request at the head that does not fit may be overtaken by later ones that
+//     do, but at most kMaxBypass times; after that admission waits for it;
+//   * launches all admitted small circuits (n <= small_qubits) together in one
+//     persistent packed kernel (state in LDS, one workgroup per circuit);
+//   * keeps the states of larger circuits resident and enqueues their gates in
+//     chunks of kChunk gates per request per iteration, each request on one of
+//     the server's streams, so new requests start while older ones still run
+//     and their kernels overlap on the device;
+//   * after a circuit's last gate enqueues its CDF, shots and expectations and
+//     copies the results to pinned host memory; an event marks completion.
+// Every request is validated and deep-copied at submission; results are
+// returned through sv_poll / sv_wait.
 #include "sv_host.h"
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <thread>
+#include <unordered_map>
+
+namespace {
+
 using namespace svh;
-extern "C" {
-sv_status sv_server_create(sv_ctx, const sv_server_opts *, sv_server *) { return fail(SV_E_UNSUPPORTED, "serving not built"); }
-sv_status sv_server_destroy(sv_server) { return fail(SV_E_UNSUPPORTED, "serving not built"); }
-sv_status sv_submit(sv_server, const sv_circuit *, uint64_t *) { return fail(SV_E_UNSUPPORTED, "serving not built"); }
-sv_status sv_poll(sv_server, uint64_t, sv_result *) { return fail(SV_E_UNSUPPORTED, "serving not built"); }
-sv_status sv_wait(sv_server, uint64_t, sv_result *, int64_t) { return fail(SV_E_UNSUPPORTED, "serving not built"); }
-sv_status sv_cancel(sv_server, uint64_t) { return fail(SV_E_UNSUPPORTED, "serving not built"); }
-sv_status sv_server_stats_get(sv_server, sv_server_stats *) { return fail(SV_E_UNSUPPORTED, "serving not built"); }
+
+constexpr int kChunk = 48;            // gates (or fused blocks) per request per driver iteration
+constexpr int kMaxBypass = 32;        // times a blocked head may be overtaken
+constexpr int kMaxBatch = 2048;       // circuits per packed launch
+constexpr int kMaxBatchGates = 1 << 19;
+constexpr int kMaxBatchesInFlight = 2;
+constexpr int kTB = 16;               // Z terms per expectation pass (matches the kernels)
+constexpr int64_t kMaxShots = 1 << 24; // shots per request (results go through pinned memory)
+constexpr int64_t kSmallMaxShots = 1 << 16;
+
+uint64_t now_ns() {
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
 }
+
+struct Req {
+    uint64_t id = 0;
+    int n = 0;
+    sv_dtype dt = SV_C64;
+    int fuse_k = 0;
+    int64_t shots = 0;
+    uint64_t seed = 0;
+    std::vector<sv_op> ops;
+    std::vector<sv_pauli> terms;
+    uint64_t t_submit = 0, t_admit = 0, t_done = 0;
+    int status = SV_OK;
+    bool small = false;
+    int bypassed = 0;
+    uint64_t footprint = 0;
+    // large path
+    sv_state st = nullptr;
+    int stream_idx = 0;
+    std::vector<Block> blocks;
+    size_t next = 0, total = 0;
+    bool measuring = false;
+    hipEvent_t ev = nullptr;
+    char *dbuf = nullptr, *hbuf = nullptr;
+    uint64_t dbytes = 0;
+    int nzb = 0;
+    std::vector<int> zi, xi;
+    // results
+    std::vector<uint64_t> samples;
+    std::vector<double> expect;
+    double weighted = 0, norm = 0;
+};
+
+struct Batch {
+    std::vector<Req *> reqs;
+    sv_dtype dt = SV_C64;
+    hipEvent_t ev = nullptr;
+    char *dbuf = nullptr, *hin = nullptr, *hout = nullptr;
+    uint64_t in_bytes = 0, out_bytes = 0, samples_total = 0, res_total = 0;
+    std::vector<uint64_t> sample_off, res_off;
+};
+
+// Bytes of the device result area of a large request: shots, then per Z
+// batch (kTB + 1) doubles, two per X/Y term, then the Z masks.
+uint64_t result_bytes(int64_t shots, int nzb, int nxz) {
+    const uint64_t nres = (uint64_t)std::max(1, nzb) * (kTB + 1) + 2ull * nxz + 1;
+    const uint64_t nmask = (uint64_t)std::max(1, nzb) * kTB;
+    return 8ull * ((uint64_t)shots + nres + nmask);
+}
+
+}  // namespace
+
+struct sv_server_s {
+    sv_ctx ctx = nullptr;
+    sv_server_opts o{};
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Req *> queue;                     // submitted, not admitted
+    std::unordered_map<uint64_t, Req *> live;    // every request not yet polled
+    std::unordered_map<uint64_t, Req *> done;    // finished, not yet polled
+    std::vector<Req *> large;                    // admitted large requests (driver)
+    std::vector<Req *> pending_small;            // admitted small requests awaiting a launch (driver)
+    std::vector<Batch *> batches;                // packed launches in flight (driver)
+    std::vector<hipStream_t> streams;
+    hipStream_t small_stream = nullptr;
+    Arena pinned;
+    char *pinned_base = nullptr;
+    uint64_t next_id = 1;
+    uint64_t held = 0, cap = 0;
+    int active = 0;
+    int rr = 0;
+    int small_c64 = 12, small_c128 = 11;
+    std::atomic<bool> stop{false};
+    std::thread driver;
+    sv_server_stats stats{};
+};
+
+namespace {
+
+void finish(sv_server s, Req *r, int status) {
+    r->status = status;
+    r->t_done = now_ns();
+    std::lock_guard<std::mutex> g(s->mu);
+    s->done[r->id] = r;
+    s->active--;
+    s->stats.completed++;
+    s->cv.notify_all();
+}
+
+void release_large(sv_server s, Req *r) {
+    if (r->ev) hipEventDestroy(r->ev);
+    r->ev = nullptr;
+    if (r->st) state_release(r->st);   // its completion event has fired
+    r->st = nullptr;
+    if (r->dbuf) s->ctx->arena.free(r->dbuf);
+    r->dbuf = nullptr;
+    if (r->hbuf) s->pinned.free(r->hbuf);
+    r->hbuf = nullptr;
+    s->held -= r->footprint;
+}
+
+// Allocate everything a large request needs; false if it does not fit now.
+bool try_admit_large(sv_server s, Req *r) {
+    if (s->held + r->footprint > s->cap) return false;
+    r->zi.clear();
+    r->xi.clear();
+    for (int t = 0; t < (int)r->terms.size(); ++t) (r->terms[t].xmask ? r->xi : r->zi).push_back(t);
+    r->nzb = (int)((r->zi.size() + kTB - 1) / kTB);
+    r->dbytes = result_bytes(r->shots, r->nzb, (int)r->xi.size());
+    r->hbuf = (char *)s->pinned.alloc(r->dbytes);
+    if (!r->hbuf) return false;
+    r->dbuf = (char *)s->ctx->arena.alloc(r->dbytes);
+    if (!r->dbuf) {
+        s->pinned.free(r->hbuf);
+        r->hbuf = nullptr;
+        return false;
+    }
+    r->stream_idx = s->rr++ % (int)s->streams.size();
+    if (svh::state_create(s->ctx, r->n, r->dt, s->streams[r->stream_idx], &r->st) != SV_OK) {
+        s->ctx->arena.free(r->dbuf);
+        s->pinned.free(r->hbuf);
+        r->dbuf = r->hbuf = nullptr;
+        return false;
+    }
+    hipEventCreateWithFlags(&r->ev, hipEventDisableTiming);
+    s->held += r->footprint;
+    if (r->fuse_k >= 2) {
+        r->blocks = plan_fusion(r->ops.data(), (int)r->ops.size(), std::min(r->fuse_k, r->n));
+        r->total = r->blocks.size();
+    } else {
+        r->total = r->ops.size();
+    }
+    r->next = 0;
+    r->measuring = false;
+    return true;
+}
+
+// Admission under the server lock.
+bool admit_locked(sv_server s) {
+    bool progress = false;
+    int scanned = 0;
+    Req *head = s->queue.empty() ? nullptr : s->queue.front();
+    for (auto it = s->queue.begin(); it != s->queue.end() && scanned < 256;) {
+        Req *r = *it;
+        ++scanned;
+        if (r->small) {
+            if ((int)s->pending_small.size() >= 4 * kMaxBatch) {
+                ++it;
+                continue;
+            }
+            r->t_admit = now_ns();
+            s->pending_small.push_back(r);
+            it = s->queue.erase(it);
+            s->active++;
+            s->stats.admitted++;
+            if (head && head != r && head->footprint > 0) head->bypassed++;
+            progress = true;
+            continue;
+        }
+        if (r->footprint > s->cap) {
+            // can never fit this server's memory
+            it = s->queue.erase(it);
+            s->active++;
+            s->stats.rejected++;
+            r->t_admit = now_ns();
+            r->status = SV_E_OOM;
+            r->t_done = r->t_admit;
+            s->done[r->id] = r;
+            s->active--;
+            s->stats.completed++;
+            s->cv.notify_all();
+            progress = true;
+            continue;
+        }
+        if ((int)s->large.size() >= s->o.max_active) {
+            // every slot for resident states is taken; small requests may still pass
+            ++it;
+            continue;
+        }
+        if (try_admit_large(s, r)) {
+            r->t_admit = now_ns();
+            s->large.push_back(r);
+            it = s->queue.erase(it);
+            s->active++;
+            s->stats.admitted++;
+            if (head && head != r) head->bypassed++;
+            s->stats.peak_bytes = std::max<uint64_t>(s->stats.peak_bytes, s->held);
+            progress = true;
+            continue;
+        }
+        // did not fit: later (smaller) requests may overtake, within limits
+        if (r == head && r->bypassed >= kMaxBypass) break;
+        ++it;
+    }
+    return progress;
+}
+
+// ---- packed launches ---------------------------------------------------------------
+bool build_gate_records(const Req *r, std::vector<svk::PGate> &gates, std::vector<double> &pool) {
+    for (const sv_op &o : r->ops) {
+        cd U[16];
+        int k, nc;
+        if (!gate_matrix(o.kind, o.p, (o.flags & SV_OP_ADJOINT) != 0, U, &k, &nc)) return false;
+        const GateDesc d = classify(U, k, o.q + nc, o.q, nc);
+        svk::PGate g{};
+        g.uoff = (uint32_t)(pool.size() / 2);
+        if (d.kind == GateDesc::NOOP) continue;
+        if (d.kind == GateDesc::GROUP) {
+            const svk::GroupGate &G = d.group;
+            g.fm = (uint32_t)G.fm;
+            g.fv = (uint32_t)G.fv;
+            g.f0 = (uint32_t)G.F[0];
+            g.f1 = (uint32_t)G.F[1];
+            g.type = G.K == 0 ? svk::PGate::PHASE : (G.K == 1 ? svk::PGate::PAIR : svk::PGate::QUAD);
+            const int cnt = G.K == 0 ? 1 : (G.K == 1 ? 4 : 16);
+            for (int i = 0; i < 2 * cnt; ++i) pool.push_back(G.U[i]);
+        } else if (d.kind == GateDesc::DIAG) {
+            const svk::DiagGate &D = d.diag;
+            if (D.k > 4) return false;
+            g.type = svk::PGate::DIAG;
+            g.k = (uint16_t)D.k;
+            g.fm = g.fv = (uint32_t)D.cmask;
+            for (int t = 0; t < D.k; ++t) g.f0 |= (uint32_t)D.targets[t] << (8 * t);
+            for (int i = 0; i < (2 << D.k); ++i) pool.push_back(D.d[i]);
+        } else {
+            return false;
+        }
+        gates.push_back(g);
+    }
+    return true;
+}
+
+bool launch_small(sv_server s) {
+    if (s->pending_small.empty() || (int)s->batches.size() >= kMaxBatchesInFlight) return false;
+    Batch *b = new Batch();
+    b->dt = s->pending_small.front()->dt;
+    std::vector<svk::PGate> gates;
+    std::vector<double> pool;
+    std::vector<svk::PCirc> circ;
+    std::vector<uint64_t> tx, tz;
+    int maxq = 1;
+    std::vector<Req *> rest;
+    for (Req *r : s->pending_small) {
+        if (r->dt != b->dt || (int)b->reqs.size() >= kMaxBatch || (int)gates.size() >= kMaxBatchGates) {
+            rest.push_back(r);
+            continue;
+        }
+        svk::PCirc c{};
+        c.n = r->n;
+        c.gate_begin = (int)gates.size();
+        build_gate_records(r, gates, pool);
+        c.gate_end = (int)gates.size();
+        c.term_begin = (int)tx.size();
+        for (auto &t : r->terms) {
+            tx.push_back(t.xmask);
+            tz.push_back(t.zmask);
+        }
+        c.term_end = (int)tx.size();
+        c.shots = r->shots;
+        c.seed = r->seed;
+        c.sample_off = b->samples_total;
+        c.res_off = b->res_total;
+        b->sample_off.push_back(b->samples_total);
+        b->res_off.push_back(b->res_total);
+        b->samples_total += (uint64_t)r->shots;
+        b->res_total += 1 + r->terms.size();
+        maxq = std::max(maxq, r->n);
+        circ.push_back(c);
+        b->reqs.push_back(r);
+    }
+    s->pending_small = rest;
+    // input layout: circ | gates | pool | tx | tz ; output: samples | res
+    auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
+    const uint64_t o_circ = 0, o_gates = al(o_circ + circ.size() * sizeof(svk::PCirc));
+    const uint64_t o_pool = al(o_gates + gates.size() * sizeof(svk::PGate));
+    const uint64_t o_tx = al(o_pool + pool.size() * sizeof(double));
+    const uint64_t o_tz = al(o_tx + tx.size() * 8);
+    b->in_bytes = al(o_tz + tz.size() * 8);
+    const uint64_t o_samp = 0, o_res = al(b->samples_total * 8);
+    b->out_bytes = al(o_res + b->res_total * 8);
+    b->hin = (char *)s->pinned.alloc(b->in_bytes);
+    b->hout = (char *)s->pinned.alloc(b->out_bytes);
+    b->dbuf = (char *)s->ctx->arena.alloc(b->in_bytes + b->out_bytes);
+    if (!b->hin || !b->hout || !b->dbuf) {
+        // not now: put the circuits back and retry next iteration
+        if (b->hin) s->pinned.free(b->hin);
+        if (b->hout) s->pinned.free(b->hout);
+        if (b->dbuf) s->ctx->arena.free(b->dbuf);
+        s->pending_small.insert(s->pending_small.begin(), b->reqs.begin(), b->reqs.end());
+        delete b;
+        return false;
+    }
+    memcpy(b->hin + o_circ, circ.data(), circ.size() * sizeof(svk::PCirc));
+    memcpy(b->hin + o_gates, gates.data(), gates.size() * sizeof(svk::PGate));
+    memcpy(b->hin + o_pool, pool.data(), pool.size() * sizeof(double));
+    memcpy(b->hin + o_tx, tx.data(), tx.size() * 8);
+    memcpy(b->hin + o_tz, tz.data(), tz.size() * 8);
+    char *din = b->dbuf, *dout = b->dbuf + b->in_bytes;
+    svk::PackedBatch pb{};
+    pb.circ = (const svk::PCirc *)(din + o_circ);
+    pb.gates = (const svk::PGate *)(din + o_gates);
+    pb.pool = (const double *)(din + o_pool);
+    pb.tx = (const uint64_t *)(din + o_tx);
+    pb.tz = (const uint64_t *)(din + o_tz);
+    pb.samples = (uint64_t *)(dout + o_samp);
+    pb.res = (double *)(dout + o_res);
+    pb.ncirc = (int)circ.size();
+    pb.max_amps = 1 << maxq;
+    pb.max_leaves = maxq > 6 ? (1 << (maxq - 6)) : 1;
+    hipStream_t st = s->small_stream;
+    hipError_t e = hipMemcpyAsync(din, b->hin, b->in_bytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+        TraceScope ts(&s->ctx->tracer, st, "packed", 0.0);
+        e = svk::launch_packed(pb, b->dt == SV_C64, maxq, 256 * 4, st);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(b->hout, dout, b->out_bytes, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(b->ev, st);
+    if (e != hipSuccess) {
+        fail(SV_E_DEVICE, std::string("packed launch: ") + hipGetErrorString(e));
+        hipStreamSynchronize(st);
+        for (Req *r : b->reqs) finish(s, r, SV_E_DEVICE);
+        s->pinned.free(b->hin);
+        s->pinned.free(b->hout);
+        s->ctx->arena.free(b->dbuf);
+        if (b->ev) hipEventDestroy(b->ev);
+        delete b;
+        return true;
+    }
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->stats.packed_launches++;
+        s->stats.packed_circuits += b->reqs.size();
+    }
+    s->batches.push_back(b);
+    return true;
+}
+
+// ---- large requests -----------------------------------------------------------------
+sv_status enqueue_measure(sv_server s, Req *r) {
+    sv_state st = r->st;
+    const hipStream_t str = st->stream;
+    if (st->is_c64() && s->ctx->renorm_period > 0 && st->gates_since_renorm > 0) {
+        sv_status q = renorm(st);
+        if (q) return q;
+    }
+    uint64_t *dsamp = (uint64_t *)r->dbuf;
+    double *dres = (double *)(r->dbuf + 8 * r->shots);
+    const uint64_t nres = (uint64_t)std::max(1, r->nzb) * (kTB + 1) + 2ull * r->xi.size() + 1;
+    uint64_t *dmask = (uint64_t *)((char *)dres + 8 * nres);
+    uint64_t *hmask = (uint64_t *)(r->hbuf + ((char *)dmask - r->dbuf));
+    const uint64_t nmask = (uint64_t)std::max(1, r->nzb) * kTB;
+    for (uint64_t i = 0; i < nmask; ++i) hmask[i] = i < r->zi.size() ? r->terms[r->zi[i]].zmask : 0;
+    SV_HIP(hipMemcpyAsync(dmask, hmask, 8 * nmask, hipMemcpyHostToDevice, str));
+    if (r->shots > 0) {
+        SV_HIP(svk::launch_cdf(st->psi, st->n, st->is_c64(), st->ws, str));
+        SV_HIP(svk::launch_sample(st->psi, st->n, st->is_c64(), st->ws, r->shots, r->seed, 0, dsamp, str));
+    }
+    for (int bz = 0; bz < std::max(1, r->nzb); ++bz) {
+        const int cnt = std::min<int>(kTB, (int)r->zi.size() - bz * kTB);
+        SV_HIP(svk::launch_expect_z(st->psi, st->n, st->is_c64(), dmask + bz * kTB, std::max(cnt, 0), st->ws,
+                                    dres + bz * (kTB + 1), str));
+    }
+    for (size_t i = 0; i < r->xi.size(); ++i)
+        SV_HIP(svk::launch_expect_xz(st->psi, st->n, st->is_c64(), r->terms[r->xi[i]].xmask, r->terms[r->xi[i]].zmask,
+                                     st->ws, dres + std::max(1, r->nzb) * (kTB + 1) + 2 * i, str));
+    SV_HIP(hipMemcpyAsync(r->hbuf, r->dbuf, 8 * (r->shots + nres), hipMemcpyDeviceToHost, str));
+    SV_HIP(hipEventRecord(r->ev, str));
+    return SV_OK;
+}
+
+void collect_large(Req *r) {
+    const uint64_t *hs = (const uint64_t *)r->hbuf;
+    const double *hr = (const double *)(r->hbuf + 8 * r->shots);
+    r->samples.assign(hs, hs + r->shots);
+    const int cnt0 = std::min<int>(kTB, (int)r->zi.size());
+    r->norm = hr[std::max(cnt0, 0)];
+    r->expect.assign(r->terms.size(), 0.0);
+    const double nrm = r->norm > 0 ? r->norm : 1.0;
+    for (size_t i = 0; i < r->zi.size(); ++i)
+        r->expect[r->zi[i]] = hr[(i / kTB) * (kTB + 1) + (i % kTB)] / nrm;
+    for (size_t i = 0; i < r->xi.size(); ++i) r->expect[r->xi[i]] = hr[std::max(1, r->nzb) * (kTB + 1) + 2 * i] / nrm;
+    r->weighted = 0;
+    for (size_t t = 0; t < r->terms.size(); ++t) r->weighted += r->terms[t].coeff * r->expect[t];
+}
+
+bool advance_large(sv_server s) {
+    bool progress = false;
+    for (Req *r : s->large) {
+        if (r->measuring) continue;
+        const int R = r->st->is_c64() ? s->ctx->renorm_period : 0;
+        int budget = kChunk;
+        sv_status q = SV_OK;
+        std::vector<cd> U;
+        while (budget > 0 && r->next < r->total && q == SV_OK) {
+            int absorbed = 1;
+            if (r->fuse_k >= 2) {
+                const Block &b = r->blocks[r->next];
+                absorbed = (int)b.ops.size();
+                if (b.ops.size() == 1) {
+                    q = apply_op(r->st, r->ops[b.ops[0]]);
+                } else {
+                    block_matrix(r->ops.data(), b, U);
+                    const int k = (int)b.qubits.size();
+                    q = k <= 2 ? apply_matrix(r->st, U.data(), k, b.qubits.data(), nullptr, 0)
+                               : apply_fused(r->st, U.data(), k, b.qubits.data());
+                }
+            } else {
+                q = apply_op(r->st, r->ops[r->next]);
+            }
+            r->next++;
+            --budget;
+            if (q == SV_OK && R > 0) {
+                r->st->gates_since_renorm += absorbed;
+                if (r->st->gates_since_renorm >= R) q = renorm(r->st);
+            }
+        }
+        if (q == SV_OK && r->next == r->total) {
+            q = enqueue_measure(s, r);
+            if (q == SV_OK) r->measuring = true;
+        }
+        if (q != SV_OK) {
+            // the request failed: wait for its stream, free it, report
+            hipStreamSynchronize(r->st->stream);
+            r->measuring = true;
+            r->status = q;
+            hipEventRecord(r->ev, r->st->stream);
+        }
+        progress = true;
+    }
+    return progress;
+}
+
+bool poll_done(sv_server s) {
+    bool progress = false;
+    for (size_t i = 0; i < s->batches.size();) {
+        Batch *b = s->batches[i];
+        if (hipEventQuery(b->ev) != hipSuccess) {
+            ++i;
+            continue;
+        }
+        const uint64_t *hs = (const uint64_t *)b->hout;
+        const double *hr = (const double *)(b->hout + ((b->samples_total * 8 + 255) & ~255ull));
+        for (size_t k = 0; k < b->reqs.size(); ++k) {
+            Req *r = b->reqs[k];
+            r->samples.assign(hs + b->sample_off[k], hs + b->sample_off[k] + r->shots);
+            r->norm = hr[b->res_off[k]];
+            r->expect.assign(hr + b->res_off[k] + 1, hr + b->res_off[k] + 1 + r->terms.size());
+            r->weighted = 0;
+            for (size_t t = 0; t < r->terms.size(); ++t) r->weighted += r->terms[t].coeff * r->expect[t];
+            finish(s, r, SV_OK);
+        }
+        hipEventDestroy(b->ev);
+        s->pinned.free(b->hin);
+        s->pinned.free(b->hout);
+        s->ctx->arena.free(b->dbuf);
+        delete b;
+        s->batches.erase(s->batches.begin() + i);
+        progress = true;
+    }
+    for (size_t i = 0; i < s->large.size();) {
+        Req *r = s->large[i];
+        if (!r->measuring || hipEventQuery(r->ev) != hipSuccess) {
+            ++i;
+            continue;
+        }
+        const int st = r->status;
+        if (st == SV_OK) collect_large(r);
+        release_large(s, r);
+        s->large.erase(s->large.begin() + i);
+        finish(s, r, st);
+        progress = true;
+    }
+    return progress;
+}
+
+void drive(sv_server s) {
+    hipSetDevice(s->ctx->device);
+    for (;;) {
+        bool progress = false;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            if (s->stop && s->queue.empty() && s->active == 0) break;
+            progress |= admit_locked(s);
+        }
+        progress |= launch_small(s);
+        progress |= advance_large(s);
+        progress |= poll_done(s);
+        if (!progress) {
+            std::unique_lock<std::mutex> lk(s->mu);
+            if (s->stop && s->queue.empty() && s->active == 0) break;
+            s->cv.wait_for(lk, std::chrono::microseconds(s->batches.empty() && s->large.empty() ? 2000 : 20));
+        }
+    }
+}
+
+sv_status validate(sv_server s, const sv_circuit *c) {
+    if (!c) return fail(SV_E_INVALID, "null circuit");
+    if (c->dtype != SV_C64 && c->dtype != SV_C128) return fail(SV_E_INVALID, "bad dtype");
+    const int nmax = c->dtype == SV_C64 ? SV_MAX_QUBITS_C64 : SV_MAX_QUBITS_C128;
+    if (c->n < 1 || c->n > nmax) return fail(SV_E_INVALID, "n out of range");
+    if (c->nops < 0 || (c->nops > 0 && !c->ops)) return fail(SV_E_INVALID, "bad op list");
+    if (c->nterms < 0 || (c->nterms > 0 && !c->terms)) return fail(SV_E_INVALID, "bad term list");
+    if (c->shots < 0 || c->shots > kMaxShots) return fail(SV_E_INVALID, "shots out of range [0, 2^24]");
+    if (c->fuse_k != 0 && (c->fuse_k < 2 || c->fuse_k > SV_MAX_FUSED)) return fail(SV_E_INVALID, "fuse_k must be 0 or 2..5");
+    for (int i = 0; i < c->nops; ++i) {
+        const sv_op &o = c->ops[i];
+        const int nq = gate_nqubits(o.kind);
+        if (nq < 0) return fail(SV_E_INVALID, "unknown gate kind at op " + std::to_string(i));
+        uint64_t m = 0;
+        for (int j = 0; j < nq; ++j) {
+            if (o.q[j] < 0 || o.q[j] >= c->n) return fail(SV_E_INVALID, "qubit out of range at op " + std::to_string(i));
+            if ((m >> o.q[j]) & 1) return fail(SV_E_INVALID, "duplicate qubit at op " + std::to_string(i));
+            m |= 1ull << o.q[j];
+        }
+        for (int j = 0; j < 3; ++j)
+            if (!std::isfinite(o.p[j])) return fail(SV_E_NUMERIC, "non-finite angle at op " + std::to_string(i));
+    }
+    const uint64_t full = (1ull << c->n) - 1;
+    for (int t = 0; t < c->nterms; ++t)
+        if ((c->terms[t].xmask | c->terms[t].zmask) & ~full) return fail(SV_E_INVALID, "Pauli mask beyond n qubits");
+    (void)s;
+    return SV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sv_status sv_server_create(sv_ctx ctx, const sv_server_opts *opts, sv_server *out) {
+    if (!ctx || !out) return fail(SV_E_INVALID, "null argument");
+    sv_server s = new sv_server_s();
+    s->ctx = ctx;
+    if (opts) s->o = *opts;
+    if (s->o.max_active <= 0) s->o.max_active = 256;
+    if (s->o.max_queue <= 0) s->o.max_queue = 1 << 20;
+    if (s->o.nstreams <= 0) s->o.nstreams = 3;
+    if (s->o.small_qubits > 0) {
+        s->small_c64 = std::min(s->o.small_qubits, 12);
+        s->small_c128 = std::min(s->o.small_qubits, 11);
+    }
+    s->cap = s->o.arena_bytes ? std::min<uint64_t>(s->o.arena_bytes, ctx->arena.size()) : ctx->arena.size();
+    const uint64_t pinned_bytes = 256ull << 20;
+    if (hipHostMalloc((void **)&s->pinned_base, pinned_bytes, hipHostMallocDefault) != hipSuccess) {
+        delete s;
+        return fail(SV_E_OOM, "pinned host buffer");
+    }
+    s->pinned.init(s->pinned_base, pinned_bytes);
+    for (int i = 0; i < s->o.nstreams; ++i) {
+        hipStream_t st;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            for (auto x : s->streams) hipStreamDestroy(x);
+            hipHostFree(s->pinned_base);
+            delete s;
+            return fail(SV_E_DEVICE, "stream creation");
+        }
+        s->streams.push_back(st);
+    }
+    hipStreamCreateWithFlags(&s->small_stream, hipStreamNonBlocking);
+    s->driver = std::thread(drive, s);
+    *out = s;
+    return SV_OK;
+}
+
+sv_status sv_server_destroy(sv_server s) {
+    if (!s) return fail(SV_E_INVALID, "null server");
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->stop = true;
+        s->cv.notify_all();
+    }
+    s->driver.join();
+    for (auto &kv : s->live) delete kv.second;
+    for (auto x : s->streams) hipStreamDestroy(x);
+    hipStreamDestroy(s->small_stream);
+    hipHostFree(s->pinned_base);
+    delete s;
+    return SV_OK;
+}
+
+sv_status sv_submit(sv_server s, const sv_circuit *c, uint64_t *req_id) {
+    if (!s || !req_id) return fail(SV_E_INVALID, "null argument");
+    sv_status v = validate(s, c);
+    if (v) return v;
+    Req *r = new Req();
+    r->n = c->n;
+    r->dt = (sv_dtype)c->dtype;
+    r->fuse_k = c->fuse_k;
+    r->shots = c->shots;
+    r->seed = c->seed;
+    r->ops.assign(c->ops, c->ops + c->nops);
+    if (c->nterms > 0) r->terms.assign(c->terms, c->terms + c->nterms);
+    r->small = r->n <= (r->dt == SV_C64 ? s->small_c64 : s->small_c128) && r->shots <= kSmallMaxShots;
+    if (r->small) {
+        std::vector<svk::PGate> g;
+        std::vector<double> p;
+        r->small = build_gate_records(r, g, p);
+    }
+    if (!r->small) {
+        const int nzb = 0;
+        int nz = 0, nx = 0;
+        for (auto &t : r->terms) (t.xmask ? nx : nz)++;
+        r->footprint = state_bytes(r->n, r->dt) + svk::measure_workspace_bytes(r->n) +
+                       result_bytes(r->shots, (nz + kTB - 1) / kTB, nx) + 3 * 256;
+        (void)nzb;
+    }
+    std::lock_guard<std::mutex> g(s->mu);
+    if ((int)s->queue.size() >= s->o.max_queue) {
+        delete r;
+        return fail(SV_E_BUSY, "server queue is full");
+    }
+    r->id = s->next_id++;
+    r->t_submit = now_ns();
+    s->queue.push_back(r);
+    s->live[r->id] = r;
+    s->stats.submitted++;
+    *req_id = r->id;
+    s->cv.notify_all();
+    return SV_OK;
+}
+
+static void copy_result(Req *r, sv_result *out) {
+    if (!out) return;
+    if (out->samples && !r->samples.empty()) memcpy(out->samples, r->samples.data(), 8 * r->samples.size());
+    if (out->expect && !r->expect.empty()) memcpy(out->expect, r->expect.data(), 8 * r->expect.size());
+    out->weighted = r->weighted;
+    out->norm = r->norm;
+    out->status = r->status;
+    out->t_submit_ns = r->t_submit;
+    out->t_admit_ns = r->t_admit;
+    out->t_done_ns = r->t_done;
+}
+
+sv_status sv_poll(sv_server s, uint64_t id, sv_result *out) {
+    if (!s) return fail(SV_E_INVALID, "null server");
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->done.find(id);
+    if (it != s->done.end()) {
+        Req *r = it->second;
+        copy_result(r, out);
+        s->done.erase(it);
+        s->live.erase(id);
+        delete r;
+        return SV_OK;
+    }
+    if (s->live.count(id)) return SV_PENDING;
+    return fail(SV_E_NOTFOUND, "unknown request id");
+}
+
+sv_status sv_wait(sv_server s, uint64_t id, sv_result *out, int64_t timeout_ms) {
+    if (!s) return fail(SV_E_INVALID, "null server");
+    std::unique_lock<std::mutex> lk(s->mu);
+    const auto deadline = std::chrono::steady_clock::now() + std::chrono::milliseconds(timeout_ms < 0 ? 0 : timeout_ms);
+    for (;;) {
+        auto it = s->done.find(id);
+        if (it != s->done.end()) {
+            Req *r = it->second;
+            copy_result(r, out);
+            s->done.erase(it);
+            s->live.erase(id);
+            delete r;
+            return SV_OK;
+        }
+        if (!s->live.count(id)) return fail(SV_E_NOTFOUND, "unknown request id");
+        if (timeout_ms < 0) {
+            s->cv.wait(lk);
+        } else if (s->cv.wait_until(lk, deadline) == std::cv_status::timeout) {
+            if (!s->done.count(id)) return SV_PENDING;
+        }
+    }
+}
+
+sv_status sv_cancel(sv_server s, uint64_t id) {
+    if (!s) return fail(SV_E_INVALID, "null server");
+    std::lock_guard<std::mutex> g(s->mu);
+    for (auto it = s->queue.begin(); it != s->queue.end(); ++it) {
+        if ((*it)->id == id) {
+            Req *r = *it;
+            s->queue.erase(it);
+            s->live.erase(id);
+            delete r;
+            s->stats.cancelled++;
+            return SV_OK;
+        }
+    }
+    if (s->live.count(id)) return fail(SV_E_BUSY, "request already admitted");
+    return fail(SV_E_NOTFOUND, "unknown request id");
+}
+
+sv_status sv_server_stats_get(sv_server s, sv_server_stats *out) {
+    if (!s || !out) return fail(SV_E_INVALID, "null argument");
+    std::lock_guard<std::mutex> g(s->mu);
+    *out = s->stats;
+    out->queued = s->queue.size();
+    out->active = (uint64_t)std::max(0, s->active);
+    return SV_OK;
+}
+
+}  // extern "C"

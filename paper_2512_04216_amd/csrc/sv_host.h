@@ -128,6 +128,20 @@ namespace svh {
 bool gate_matrix(int kind, const double *p, bool adjoint, cd *U, int *k, int *nc);
 int gate_nqubits(int kind);
 
+// Classification of a gate matrix (exact comparisons): a phase on one
+// subspace or a two-level unitary or a dense two-qubit matrix (GROUP), a
+// general diagonal (DIAG), the identity (NOOP), or anything wider (DENSE).
+struct GateDesc {
+    enum Kind { NOOP, GROUP, DIAG, DENSE } kind = NOOP;
+    svk::GroupGate group;
+    svk::DiagGate diag;
+};
+GateDesc classify(const cd *U, int k, const int *targets, const int *controls, int nc);
+// algorithmic bytes of one launch of d on n qubits, s bytes per amplitude
+double desc_bytes(const GateDesc &d, int n, int s);
+
+// apply one named op (sv_op) on a state
+sv_status apply_op(sv_state st, const sv_op &o);
 // apply one matrix gate on a state (classification + launch)
 sv_status apply_matrix(sv_state st, const cd *U, int k, const int *targets, const int *controls, int nc);
 // dense block via the fused kernels
@@ -144,6 +158,11 @@ void block_matrix(const sv_op *ops, const Block &b, std::vector<cd> &U);
 
 // measurement drivers
 sv_status norm_device(sv_state st);   // leaves ||psi||^2 at norm2_dev_ptr
+sv_status renorm(sv_state st);        // psi <- psi / ||psi|| on the state's stream
+// free a state without waiting for its stream (its work must be complete)
+sv_status state_release(sv_state st);
+// allocate a state on a given stream (sv_create uses the context's stream)
+sv_status state_create(sv_ctx c, int n, sv_dtype dt, hipStream_t stream, sv_state *out);
 uint64_t state_bytes(int n, sv_dtype dt);
 
 }  // namespace svh

@@ -73,4 +73,39 @@ hipError_t launch_expect_z(const void *psi, int n, int is_c64, const uint64_t *z
 hipError_t launch_expect_xz(const void *psi, int n, int is_c64, uint64_t xmask, uint64_t zmask,
                             void *ws, double *out_dev, hipStream_t s);
 
+// ---- packed small circuits (one workgroup per circuit, state in LDS) ------
+struct PGate {
+    enum Type : uint16_t { PHASE = 0, PAIR = 1, QUAD = 2, DIAG = 3 };
+    uint16_t type;
+    uint16_t k;        // DIAG: number of targets (<= 4)
+    uint32_t fm, fv;   // fixed-bit mask / value; DIAG: controls in both
+    uint32_t f0, f1;   // flip vectors; DIAG: f0 holds the target positions, one per byte
+    uint32_t uoff;     // first complex entry in the matrix pool
+};
+
+struct PCirc {
+    int32_t n;
+    int32_t gate_begin, gate_end;
+    int32_t term_begin, term_end;
+    int32_t pad;
+    int64_t shots;
+    uint64_t seed;
+    uint64_t sample_off;   // first entry in PackedBatch::samples
+    uint64_t res_off;      // res[res_off] = squared norm, then one value per term
+};
+
+struct PackedBatch {
+    const PGate *gates;
+    const double *pool;    // complex128 entries (re, im)
+    const PCirc *circ;
+    int ncirc;
+    int max_amps, max_leaves;
+    const uint64_t *tx, *tz;
+    uint64_t *samples;
+    double *res;
+};
+
+uint64_t packed_lds_bytes(int max_qubits, int is_c64);
+hipError_t launch_packed(const PackedBatch &b, int is_c64, int max_qubits, int max_blocks, hipStream_t s);
+
 }  // namespace svk

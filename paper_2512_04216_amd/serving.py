@@ -1,7 +1,92 @@
-"""Serving front end (binding of sv_server_* / sv_submit / sv_poll)."""
+"""Binding of the request server (sv_server_create / sv_submit / sv_poll / sv_wait /
+sv_cancel): argument marshalling only; admission, batching and execution run in
+the library's driver thread and kernels."""
 from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _abi
+from ._abi import SV_OK, SV_PENDING, check
+
+
+def _lib():
+    return _abi.load()
 
 
 class Server:
-    def __init__(self, *a, **k):
-        raise NotImplementedError("serving loop not built yet")
+    """Continuous-batching server over a Context (see include/sv.h)."""
+
+    def __init__(self, ctx, arena_bytes: int = 0, max_active: int = 0, small_qubits: int = 0,
+                 max_queue: int = 0, nstreams: int = 0):
+        from . import ops_to_array, terms_to_array  # noqa: F401  (same package)
+
+        self.ctx = ctx
+        opts = _abi.sv_server_opts(arena_bytes=int(arena_bytes), max_active=int(max_active),
+                                   small_qubits=int(small_qubits), max_queue=int(max_queue),
+                                   nstreams=int(nstreams))
+        h = ctypes.c_void_p()
+        check(_lib().sv_server_create(ctx.handle, ctypes.byref(opts), ctypes.byref(h)))
+        self.handle = h
+        self._shape = {}
+
+    def submit(self, n, ops, shots=0, seed=0, terms=(), dtype="c64", fuse_k=0) -> int:
+        from . import _dtype_code, ops_to_array, terms_to_array
+
+        oa = ops_to_array(ops)
+        ta = terms_to_array(terms)
+        c = _abi.sv_circuit(n=int(n), dtype=_dtype_code(dtype), ops=oa, nops=len(ops), fuse_k=int(fuse_k),
+                            shots=int(shots), seed=int(seed) & (2**64 - 1), terms=ta, nterms=len(terms))
+        rid = ctypes.c_uint64()
+        check(_lib().sv_submit(self.handle, ctypes.byref(c), ctypes.byref(rid)))
+        self._shape[rid.value] = (int(shots), len(terms))
+        return rid.value
+
+    def _result(self, rid, fn, *extra):
+        shots, nterms = self._shape.get(rid, (0, 0))
+        samples = np.zeros(max(1, shots), dtype=np.uint64)
+        expect = np.zeros(max(1, nterms), dtype=np.float64)
+        res = _abi.sv_result(samples=samples.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                             expect=expect.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        st = fn(self.handle, ctypes.c_uint64(rid), ctypes.byref(res), *extra)
+        if st == SV_PENDING:
+            return None
+        check(st)
+        self._shape.pop(rid, None)
+        return {"status": res.status, "samples": samples[:shots], "expect": expect[:nterms],
+                "weighted": res.weighted, "norm": res.norm, "t_submit_ns": res.t_submit_ns,
+                "t_admit_ns": res.t_admit_ns, "t_done_ns": res.t_done_ns}
+
+    def poll(self, rid: int):
+        """Result dict once finished, else None (non-blocking)."""
+        return self._result(rid, _lib().sv_poll)
+
+    def wait(self, rid: int, timeout_ms: int = -1):
+        return self._result(rid, _lib().sv_wait, ctypes.c_int64(int(timeout_ms)))
+
+    def cancel(self, rid: int) -> bool:
+        st = _lib().sv_cancel(self.handle, ctypes.c_uint64(rid))
+        if st == SV_OK:
+            self._shape.pop(rid, None)
+            return True
+        if st == _abi.SV_E_BUSY:
+            return False
+        check(st)
+        return False
+
+    def stats(self):
+        s = _abi.sv_server_stats()
+        check(_lib().sv_server_stats_get(self.handle, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in _abi.sv_server_stats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            check(_lib().sv_server_destroy(self.handle))
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

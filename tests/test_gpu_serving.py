@@ -1,0 +1,117 @@
+"""GPU tests of the request server: results match the oracle, each result is
+the same alone and in the mix (bitwise), footprint admission with back-pressure
+and rejection, cancellation and validation."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _requests(seed, count, n_lo, n_hi, dtypes=("c64", "c128"), fuse=(0,)):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(count):
+        n = int(rng.integers(n_lo, n_hi + 1))
+        d = int(rng.integers(3, 12))
+        ops = W.serving_circuit(n, d, rng)
+        terms = W.random_paulis(n, int(rng.integers(0, 5)), seed=seed * 1000 + i)
+        terms += [(0, int(rng.integers(1, 1 << n)), 1.0)]
+        reqs.append({"n": n, "ops": ops, "shots": int(rng.integers(0, 2000)), "seed": seed * 7919 + i,
+                     "terms": terms, "dtype": dtypes[i % len(dtypes)], "fuse_k": fuse[i % len(fuse)]})
+    return reqs
+
+
+def _submit(srv, r):
+    return srv.submit(r["n"], r["ops"], shots=r["shots"], seed=r["seed"], terms=r["terms"],
+                      dtype=r["dtype"], fuse_k=r["fuse_k"])
+
+
+def _check_vs_oracle(O, r, res):
+    assert res["status"] == 0
+    psi = O.run(r["ops"], r["n"])
+    want_s = O.sample(psi, r["shots"], r["seed"])
+    got_s = res["samples"]
+    assert got_s.shape == want_s.shape
+    assert np.all(got_s < (1 << r["n"]))
+    mism = int(np.sum(got_s != want_s))
+    want_e = np.array([O.expect(psi, x, z).real for x, z, _ in r["terms"]])
+    if r["dtype"] == "c128":
+        assert mism <= 1
+        assert np.max(np.abs(res["expect"] - want_e)) <= 1e-12
+        assert abs(res["norm"] - 1.0) <= 1e-12
+    else:
+        assert mism <= max(3, 0.01 * r["shots"])
+        assert np.max(np.abs(res["expect"] - want_e)) <= 2 * math.sqrt(1e-5)
+        assert abs(res["norm"] - 1.0) <= 1e-4
+
+
+def test_serving_matches_oracle(ctx, S, O):
+    reqs = _requests(1, 80, 3, 16, fuse=(0, 0, 5))
+    with S.Server(ctx) as srv:
+        ids = [_submit(srv, r) for r in reqs]
+        results = [srv.wait(i, 60000) for i in ids]
+        st = srv.stats()
+    assert st["completed"] == len(reqs) and st["packed_circuits"] > 0
+    for r, res in zip(reqs, results):
+        assert res is not None
+        _check_vs_oracle(O, r, res)
+        assert res["t_submit_ns"] <= res["t_admit_ns"] <= res["t_done_ns"]
+
+
+def test_alone_equals_mix_bitwise(ctx, S):
+    reqs = _requests(2, 48, 4, 20, fuse=(0, 5))
+    with S.Server(ctx) as srv:
+        alone = []
+        for r in reqs:
+            alone.append(srv.wait(_submit(srv, r), 60000))
+        ids = [_submit(srv, r) for r in reqs]
+        mixed = [srv.wait(i, 60000) for i in ids]
+    for a, m in zip(alone, mixed):
+        assert a["status"] == 0 and m["status"] == 0
+        assert np.array_equal(a["samples"], m["samples"])
+        assert np.array_equal(a["expect"], m["expect"])
+        assert a["norm"] == m["norm"]
+
+
+def test_footprint_admission_and_rejection(ctx, S):
+    cap = 80 << 20                 # room for two 2^22 complex64 states (32 MiB each) and workspaces
+    rng = np.random.default_rng(3)
+    with S.Server(ctx, arena_bytes=cap) as srv:
+        ids = []
+        for i in range(6):
+            ops = W.serving_circuit(22, 3, rng)
+            ids.append(srv.submit(22, ops, shots=100, seed=i, dtype="c64"))
+        big = srv.submit(24, [("h", (0,), ())], shots=10, seed=1, dtype="c64")   # 128 MiB > cap
+        out = [srv.wait(i, 60000) for i in ids]
+        rb = srv.wait(big, 60000)
+        st = srv.stats()
+    assert all(o["status"] == 0 for o in out)
+    assert rb["status"] == S._abi.SV_E_OOM
+    assert st["peak_bytes"] <= cap and st["rejected"] == 1
+    # the six large requests could not all be resident together
+    admits = sorted(o["t_admit_ns"] for o in out)
+    dones = sorted(o["t_done_ns"] for o in out)
+    assert admits[-1] >= dones[0]
+
+
+def test_cancel_unknown_and_validation(ctx, S):
+    rng = np.random.default_rng(4)
+    with S.Server(ctx, arena_bytes=80 << 20) as srv:
+        ids = [srv.submit(22, W.serving_circuit(22, 20, rng), shots=10, seed=i) for i in range(8)]
+        assert srv.cancel(ids[-1]) is True
+        with pytest.raises(S.SvError) as e:
+            srv.poll(ids[-1])
+        assert e.value.status == S._abi.SV_E_NOTFOUND
+        with pytest.raises(S.SvError):
+            srv.poll(123456789)
+        with pytest.raises(S.SvError) as e:
+            srv.submit(5, [("cx", (1, 7), ())])
+        assert e.value.status == S._abi.SV_E_INVALID
+        with pytest.raises(S.SvError):
+            srv.submit(5, [("h", (0,), ())], terms=[(1 << 6, 0, 1.0)])
+        for i in ids[:-1]:
+            assert srv.wait(i, 60000)["status"] == 0
