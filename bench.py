@@ -153,6 +153,158 @@ def stream_copy_gbps(nbytes=4 << 30, reps=5):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
+# ---------------------------------------------------------------- other workloads
+def bench_fused(S, steps=1):
+    """33-qubit complex128 and 34-qubit complex64 brickwork (10 layers): gates
+    fused greedily into <= 5-qubit dense blocks on MFMA vs one kernel per gate."""
+    import torch
+
+    import workloads as W
+
+    out = {}
+    ctx = S.Context(arena_bytes=140 << 30)
+    for n, dt in ((33, "c128"), (34, "c64")):
+        ops = W.brickwork(n, 10, seed=SEED + 2)
+        arr = S.ops_to_numpy(ops)
+        st = S.State(ctx, n, dt)
+        res = {"gates": len(ops)}
+        nb, ns = S.sv_plan_fusion(ops, n, 5)
+        res["fused_blocks"] = nb
+        for fk in (5, 0):
+            st.reset(0)
+            torch.cuda.synchronize()
+            ctx.trace_read()
+            ctx.trace(True)
+            t0 = time.perf_counter()
+            st.run(arr, fuse_k=fk)
+            torch.cuda.synchronize()
+            dt_s = time.perf_counter() - t0
+            ctx.trace(False)
+            tr = ctx.trace_read()
+            key = "fused" if fk else "unfused"
+            res[key] = {"seconds": round(dt_s, 3), "gates_per_s": round(len(ops) / dt_s, 2)}
+            if fk and "fused_mfma" in tr:
+                rec = tr["fused_mfma"]
+                avg = rec["seconds"] / rec["launches"]
+                amps = float(1 << n)
+                flops = 256.0 * amps        # 8 * 2^k flop per amplitude, k = 5 (4-qubit blocks count as 5)
+                peak = 78.6 if dt == "c128" else 157.3
+                res[key]["mfma_kernel"] = {"launches": rec["launches"], "avg_ms": round(avg * 1e3, 3),
+                                           "GBps": round(rec["bytes"] / rec["launches"] / avg / 1e9, 1),
+                                           "TFLOPs": round(flops / avg / 1e12, 2), "peak_TFLOPs": peak,
+                                           "mfma_frac": round(flops / avg / 1e12 / peak, 3)}
+            print("bench fused: %dq %s fuse_k=%d %.2f s" % (n, dt, fk, dt_s), file=sys.stderr, flush=True)
+        st.close()
+        out["%dq_%s" % (n, dt)] = res
+    ctx.close()
+    return out
+
+
+def bench_qaoa(S):
+    """30-qubit QAOA MaxCut p=20 on a seeded random 3-regular graph; energy
+    <H_cost> = sum over edges of <Z_u Z_v>, complex64 vs complex128."""
+    import torch
+
+    import workloads as W
+
+    n, p = 30, 20
+    ops, edges, terms = W.qaoa_maxcut(n, p, seed=SEED + 4)
+    arr = S.ops_to_numpy(ops)
+    ctx = S.Context(arena_bytes=40 << 30)
+    out = {"gates": len(ops), "edges": len(edges)}
+    for dt in ("c128", "c64"):
+        st = S.State(ctx, n, dt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st.run(arr)
+        torch.cuda.synchronize()
+        t_run = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        vals, energy = st.expect(terms)
+        t_exp = time.perf_counter() - t0
+        out[dt] = {"run_s": round(t_run, 3), "gates_per_s": round(len(ops) / t_run, 1), "expect_s": round(t_exp, 4),
+                   "energy": energy, "norm2": st.norm2()}
+        st.close()
+    out["energy_abs_diff_c64_vs_c128"] = abs(out["c64"]["energy"] - out["c128"]["energy"])
+    ctx.close()
+    return out
+
+
+def bench_serving(S, count=10000, baseline_count=300, load=0.8):
+    """Serving stream: `count` circuits, n uniform 8..26, depth uniform 5..40,
+    gates uniform from {H,S,T,RX,RY,RZ,CNOT,CZ,SWAP}, 1000 shots, complex64.
+    (1) saturated: every request submitted at t=0 -> circuits/s;
+    (2) Poisson arrivals at load * saturated rate -> p50/p99 latency;
+    (3) baseline: plain complex128, one circuit at a time, one kernel per gate,
+        on the first `baseline_count` circuits."""
+    import torch
+
+    import workloads as W
+
+    t0 = time.perf_counter()
+    reqs = W.serving_stream(count, seed=SEED + 3)
+    arrs = [S.ops_to_numpy(r["ops"]) for r in reqs]
+    print("bench serving: generated %d circuits in %.1f s" % (count, time.perf_counter() - t0), file=sys.stderr,
+          flush=True)
+    ctx = S.Context(arena_bytes=200 << 30)
+    out = {"circuits": count}
+
+    def run(fuse_k, arrivals=None):
+        with S.Server(ctx) as srv:
+            ids = []
+            t_start = time.perf_counter()
+            for i, r in enumerate(reqs):
+                if arrivals is not None:
+                    while time.perf_counter() - t_start < arrivals[i]:
+                        pass
+                ids.append(srv.submit(r["n"], arrs[i], shots=r["shots"], seed=r["seed"], dtype="c64",
+                                      fuse_k=fuse_k))
+            res = [srv.wait(i, 600000) for i in ids]
+            st = srv.stats()
+        sub = np.array([x["t_submit_ns"] for x in res], dtype=np.float64)
+        done = np.array([x["t_done_ns"] for x in res], dtype=np.float64)
+        lat = (done - sub) / 1e6
+        span = (done.max() - sub.min()) / 1e9
+        bad = sum(1 for x in res if x["status"] != 0)
+        return {"circuits_per_s": round(count / span, 1), "span_s": round(span, 3),
+                "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                "failed": bad, "packed_launches": st["packed_launches"], "packed_circuits": st["packed_circuits"],
+                "peak_state_GB": round(st["peak_bytes"] / 1e9, 2)}
+
+    import numpy as np  # noqa: F811
+
+    best = None
+    for fk in (5, 0):
+        r = run(fk)
+        out["saturated_fuse%d" % fk] = r
+        print("bench serving: saturated fuse_k=%d %s" % (fk, r), file=sys.stderr, flush=True)
+        if best is None or r["circuits_per_s"] > best[1]["circuits_per_s"]:
+            best = (fk, r)
+    fk, sat = best
+    rate = load * sat["circuits_per_s"]
+    arr_t = W.poisson_arrivals(count, rate, seed=SEED + 5)
+    r = run(fk, arrivals=arr_t)
+    r["arrival_rate"] = round(rate, 1)
+    r["fuse_k"] = fk
+    out["poisson_%.2f" % load] = r
+    print("bench serving: poisson %s" % r, file=sys.stderr, flush=True)
+    # baseline: complex128 one circuit at a time, per-gate kernels
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(baseline_count):
+        rq = reqs[i]
+        st = S.State(ctx, rq["n"], "c128")
+        st.run(arrs[i])
+        st.sample(rq["shots"], rq["seed"])
+        st.close()
+    torch.cuda.synchronize()
+    dtb = time.perf_counter() - t0
+    out["baseline_c128_one_at_a_time"] = {"circuits": baseline_count, "seconds": round(dtb, 3),
+                                          "circuits_per_s": round(baseline_count / dtb, 1)}
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -162,6 +314,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c64", action="store_true", help="skip the complex64 side measurement")
     ap.add_argument("--no-trace", action="store_true")
+    ap.add_argument("--config", default="28q", choices=["28q", "fused", "qaoa", "serving"],
+                    help="28q (default): the headline line; the others print their own JSON line")
+    ap.add_argument("--serving-count", type=int, default=10000)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (no sharding or collectives); use --gpus 1",
@@ -173,6 +328,11 @@ def main():
     import paper_2512_04216_amd as S
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.config != "28q":
+        fn = {"fused": lambda: bench_fused(S), "qaoa": lambda: bench_qaoa(S),
+              "serving": lambda: bench_serving(S, count=args.serving_count)}[args.config]
+        print(json.dumps({"config": args.config, "result": fn()}))
+        return
     print("bench: 28-qubit brickwork + QFT, %s, %d warmup + %d timed steps" % (args.dtype, args.warmup, args.steps),
           file=sys.stderr, flush=True)
     copy_gbps = stream_copy_gbps()

@@ -101,6 +101,10 @@ sv_status sv_set_stream(sv_state st, void *stream);
 sv_status sv_synchronize(sv_state st);
 /* Device address of the amplitudes and their byte size (read-only use by the caller). */
 sv_status sv_device_ptr(sv_state st, void **ptr, uint64_t *bytes);
+/* Gather `count` amplitudes psi[idx[i]] (each idx < 2^n) into out as interleaved
+ * (re, im) doubles (2 * count entries, caller-owned); waits for the state's stream.
+ * Lets a caller inspect chosen outputs of a state too large to copy out. */
+sv_status sv_get_amplitudes(sv_state st, const uint64_t *idx, int64_t count, double *out);
 /* Copy the amplitudes to / from host memory; bytes must equal the state's size. */
 sv_status sv_copy_out(sv_state st, void *host_dst, uint64_t bytes);
 sv_status sv_copy_in(sv_state st, const void *host_src, uint64_t bytes);
@@ -147,10 +151,12 @@ sv_status sv_gate_matrix(int kind, const double *params, int adjoint, double *U_
                          int *k_out, int *ncontrols_out);
 
 /* Run a gate list in order. fuse_k = 0 launches one kernel per gate; 2..5 first
- * groups consecutive gates greedily into blocks of at most fuse_k qubits
- * (block matrix = product of the embedded gate matrices, formed in complex128
- * on the host) and applies each block with sv_apply_fused's kernels. Gates that
- * only change a phase on a subspace are never fused. */
+ * groups the gates greedily into blocks of at most fuse_k qubits (a gate joins
+ * the open block(s) sharing its qubits while their union stays within fuse_k;
+ * the block matrix is the product of the embedded gate matrices, formed in
+ * complex128 on the host) and applies each block of 3 or more qubits with
+ * sv_apply_fused's kernels (MFMA). With fuse_k > 0 the order of gates on
+ * disjoint qubits may change; the result is the same up to rounding. */
 sv_status sv_run(sv_state st, const sv_op *ops, int nops, int fuse_k);
 
 /* Fusion plan of a gate list without running it: number of blocks and of ops

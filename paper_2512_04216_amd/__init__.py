@@ -34,19 +34,30 @@ def _dtype_code(dtype) -> int:
     raise ValueError("dtype must be complex64 or complex128")
 
 
-def ops_to_array(ops):
-    """Gate list [(name, qubits, params)] or [(name, qubits, params, adjoint)] -> sv_op array."""
-    arr = (sv_op * max(1, len(ops)))()
+SV_OP_DTYPE = np.dtype([("kind", "<i4"), ("flags", "<i4"), ("q", "<i4", 3), ("pad", "<i4"), ("p", "<f8", 3)])
+
+
+def ops_to_numpy(ops) -> np.ndarray:
+    """Gate list [(name, qubits, params[, adjoint])] -> numpy array laid out as sv_op."""
+    a = np.zeros(max(1, len(ops)), dtype=SV_OP_DTYPE)
     for i, op in enumerate(ops):
-        name, qubits, params = op[0], op[1], op[2]
-        adj = bool(op[3]) if len(op) > 3 else False
-        o = arr[i]
-        o.kind = GATE_KIND[name]
-        o.flags = SV_OP_ADJOINT if adj else 0
-        for j, q in enumerate(qubits):
-            o.q[j] = int(q)
-        for j, p in enumerate(params):
-            o.p[j] = float(p)
+        a["kind"][i] = GATE_KIND[op[0]]
+        if len(op) > 3 and op[3]:
+            a["flags"][i] = SV_OP_ADJOINT
+        q = op[1]
+        a["q"][i, : len(q)] = q
+        p = op[2]
+        if p:
+            a["p"][i, : len(p)] = p
+    return a
+
+
+def ops_to_array(ops):
+    """Gate list -> ctypes sv_op array (or pass through an array from ops_to_numpy)."""
+    if isinstance(ops, np.ndarray):
+        return ops.ctypes.data_as(ctypes.POINTER(sv_op))
+    a = ops_to_numpy(ops)
+    arr = (sv_op * len(a)).from_buffer_copy(a.tobytes())
     return arr
 
 
@@ -204,6 +215,8 @@ class State:
 
     def run(self, ops, fuse_k: int = 0):
         arr = ops_to_array(ops)
+        if isinstance(ops, np.ndarray) and ops.dtype != SV_OP_DTYPE:
+            raise TypeError("op arrays must use SV_OP_DTYPE")
         check(lib().sv_run(self.handle, arr, len(ops), int(fuse_k)))
         return self
 
@@ -230,6 +243,14 @@ class State:
         check(lib().sv_expect(self.handle, arr, len(terms), vals.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                               ctypes.byref(w)))
         return vals[: len(terms)], w.value
+
+    def amplitudes(self, idx) -> np.ndarray:
+        """psi[idx] as complex128 (a device gather; the state stays resident)."""
+        idx = np.ascontiguousarray(np.asarray(idx, dtype=np.uint64))
+        out = np.zeros(2 * max(1, idx.size), dtype=np.float64)
+        check(lib().sv_get_amplitudes(self.handle, idx.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), idx.size,
+                                      out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out[: 2 * idx.size].view(np.complex128)
 
     def copy_out(self) -> np.ndarray:
         out = np.empty(1 << self.n, dtype=self.np_dtype)

@@ -90,6 +90,7 @@ PROTOTYPES = {
     "sv_set_stream": [P, P],
     "sv_synchronize": [P],
     "sv_device_ptr": [P, ctypes.POINTER(P), U64P],
+    "sv_get_amplitudes": [P, U64P, I64, DP],
     "sv_copy_out": [P, P, U64],
     "sv_copy_in": [P, P, U64],
     "sv_apply_gate": [P, DP, I32, IP, IP, I32],

@@ -399,6 +399,25 @@ sv_status sv_device_ptr(sv_state st, void **ptr, uint64_t *bytes) {
     return SV_OK;
 }
 
+sv_status sv_get_amplitudes(sv_state st, const uint64_t *idx, int64_t count, double *out) {
+    if (!st || (count > 0 && (!idx || !out)) || count < 0) return fail(SV_E_INVALID, "bad argument");
+    if (count == 0) return SV_OK;
+    const uint64_t N = 1ull << st->n;
+    for (int64_t i = 0; i < count; ++i)
+        if (idx[i] >= N) return fail(SV_E_INVALID, "amplitude index >= 2^n");
+    char *buf = (char *)st->ctx->arena.alloc(24ull * count);
+    if (!buf) return fail(SV_E_OOM, "arena cannot hold the gather buffers");
+    uint64_t *didx = (uint64_t *)buf;
+    double *dout = (double *)(buf + 8ull * count);
+    hipError_t e = hipMemcpyAsync(didx, idx, 8ull * count, hipMemcpyHostToDevice, st->stream);
+    if (e == hipSuccess) e = svk::launch_gather(st->psi, st->is_c64(), didx, count, dout, st->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, dout, 16ull * count, hipMemcpyDeviceToHost, st->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+    st->ctx->arena.free(buf);
+    if (e != hipSuccess) return hip_fail(e, "amplitude gather");
+    return SV_OK;
+}
+
 sv_status sv_copy_out(sv_state st, void *dst, uint64_t bytes) {
     if (!st || !dst) return fail(SV_E_INVALID, "null argument");
     const uint64_t want = (1ull << st->n) * (st->is_c64() ? 8 : 16);

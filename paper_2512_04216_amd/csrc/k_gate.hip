@@ -289,6 +289,16 @@ __global__ __launch_bounds__(kBlock) void k_scale(u4 *__restrict__ psi, uint64_t
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gather(const Cx<T> *__restrict__ psi, const uint64_t *__restrict__ idx,
+                                                   int64_t count, double *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= count) return;
+    const Cx<T> a = psi[idx[i]];
+    out[2 * i] = (double)a.re;
+    out[2 * i + 1] = (double)a.im;
+}
+
 inline int popc64(uint64_t x) { return __builtin_popcountll(x); }
 
 uint64_t oneshot_blocks(uint64_t nvec) {
@@ -316,8 +326,7 @@ template <typename T, int KH, int KL, bool MIX>
 hipError_t go_group(const GArgs<T> &a, void *psi, hipStream_t s) {
     const uint64_t waves = (a.n_outer + kSlots - 1) / kSlots;
     const uint64_t blocks = (waves + (kBlock / 64) - 1) / (kBlock / 64);
-    hipLaunchKernelGGL((k_group<T, KH, KL, MIX>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a,
-                       (u4 *)psi);
+    hipLaunchKernelGGL((k_group<T, KH, KL, MIX>), svk::grid_for(blocks), dim3(kBlock), 0, s, a, (u4 *)psi);
     return hipGetLastError();
 }
 
@@ -411,7 +420,7 @@ hipError_t launch_diag_t(const svk::DiagGate &g, void *psi, int n, hipStream_t s
     for (int m = 0; m < (2 << g.k); ++m) a.d[m] = (T)g.d[m];
     const uint64_t waves = (a.n_outer + kSlots - 1) / kSlots;
     const uint64_t blocks = (waves + 3) / 4;
-    hipLaunchKernelGGL((k_diag<T>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a, (u4 *)psi);
+    hipLaunchKernelGGL((k_diag<T>), svk::grid_for(blocks), dim3(kBlock), 0, s, a, (u4 *)psi);
     return hipGetLastError();
 }
 
@@ -423,9 +432,9 @@ hipError_t launch_init(void *psi, int n, int is_c64, uint64_t basis, hipStream_t
     const uint64_t nvec = is_c64 ? ((1ull << n) + 1) / 2 : (1ull << n);
     const uint64_t blocks = oneshot_blocks(nvec);
     if (is_c64)
-        hipLaunchKernelGGL(k_init<float>, dim3((unsigned)blocks), dim3(kBlock), 0, s, (u4 *)psi, nvec, basis);
+        hipLaunchKernelGGL(k_init<float>, grid_for(blocks), dim3(kBlock), 0, s, (u4 *)psi, nvec, basis);
     else
-        hipLaunchKernelGGL(k_init<double>, dim3((unsigned)blocks), dim3(kBlock), 0, s, (u4 *)psi, nvec, basis);
+        hipLaunchKernelGGL(k_init<double>, grid_for(blocks), dim3(kBlock), 0, s, (u4 *)psi, nvec, basis);
     return hipGetLastError();
 }
 
@@ -437,13 +446,26 @@ hipError_t launch_diag(const DiagGate &g, void *psi, int n, int is_c64, hipStrea
     return is_c64 ? launch_diag_t<float>(g, psi, n, s) : launch_diag_t<double>(g, psi, n, s);
 }
 
+hipError_t launch_gather(const void *psi, int is_c64, const uint64_t *idx_dev, int64_t count, double *out_dev,
+                         hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((count + kBlock - 1) / kBlock);
+    if (is_c64)
+        hipLaunchKernelGGL(k_gather<float>, dim3(blocks), dim3(kBlock), 0, s, (const Cx<float> *)psi, idx_dev, count,
+                           out_dev);
+    else
+        hipLaunchKernelGGL(k_gather<double>, dim3(blocks), dim3(kBlock), 0, s, (const Cx<double> *)psi, idx_dev, count,
+                           out_dev);
+    return hipGetLastError();
+}
+
 hipError_t launch_scale_by_norm(void *psi, int n, int is_c64, const double *norm2_dev, hipStream_t s) {
     const uint64_t nvec = is_c64 ? ((1ull << n) + 1) / 2 : (1ull << n);
     const uint64_t blocks = oneshot_blocks(nvec);
     if (is_c64)
-        hipLaunchKernelGGL(k_scale<float>, dim3((unsigned)blocks), dim3(kBlock), 0, s, (u4 *)psi, nvec, norm2_dev);
+        hipLaunchKernelGGL(k_scale<float>, grid_for(blocks), dim3(kBlock), 0, s, (u4 *)psi, nvec, norm2_dev);
     else
-        hipLaunchKernelGGL(k_scale<double>, dim3((unsigned)blocks), dim3(kBlock), 0, s, (u4 *)psi, nvec, norm2_dev);
+        hipLaunchKernelGGL(k_scale<double>, grid_for(blocks), dim3(kBlock), 0, s, (u4 *)psi, nvec, norm2_dev);
     return hipGetLastError();
 }
 

@@ -374,13 +374,14 @@ __global__ __launch_bounds__(256) void k_zbatch(const u4 *__restrict__ psi, int 
     }
 #pragma unroll
     for (int t = 0; t < kTB; ++t) {
-        if (t >= nterms) break;
-        const DD twoS{2.0 * S[t].s, 2.0 * S[t].c};
-        DD v = ((lanebits >> t) & 1) ? dd_add(twoS, DD{-P.s, -P.c}) : dd_add(P, DD{-twoS.s, -twoS.c});
-        v = wave_reduce_dd(v, lane);
-        if (lane == 0) {
-            red[wv][t][0] = v.s;
-            red[wv][t][1] = v.c;
+        if (t < nterms) {   // wavefront-uniform
+            const DD twoS{2.0 * S[t].s, 2.0 * S[t].c};
+            DD v = ((lanebits >> t) & 1) ? dd_add(twoS, DD{-P.s, -P.c}) : dd_add(P, DD{-twoS.s, -twoS.c});
+            v = wave_reduce_dd(v, lane);
+            if (lane == 0) {
+                red[wv][t][0] = v.s;
+                red[wv][t][1] = v.c;
+            }
         }
     }
     __syncthreads();
@@ -442,13 +443,16 @@ __global__ __launch_bounds__(256) void k_expect_xz(const u4 *__restrict__ psi, i
         const int nseg = xh ? 2 : 1;
         Q seg[2];
         uint64_t sbase[2] = {baseA, baseA ^ xh};
-        for (int s = 0; s < nseg; ++s) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
             seg[s].v = u4{0, 0, 0, 0};
-            if (lane_valid) seg[s].v = ld_nt(psi + (sbase[s] >> LGE) + lane);
+            if (s < nseg && lane_valid) seg[s].v = ld_nt(psi + (sbase[s] >> LGE) + lane);
         }
         double pr = 0.0, pi = 0.0;
-        for (int s = 0; s < nseg; ++s) {
-            const Q &src = seg[xh ? (s ^ 1) : s];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            if (s >= nseg) continue;   // wavefront-uniform
+            const Q src = xh ? seg[s ^ 1] : seg[s];
             const Q partner = lx ? lane_xor(src, lane, lx) : src;
             if (!lane_valid) continue;
 #pragma unroll
@@ -515,11 +519,11 @@ const double *norm2_dev_ptr(const void *ws, int n) { return wsd(ws) + ws_layout(
 hipError_t launch_cdf(const void *psi, int n, int is_c64, void *ws, hipStream_t s) {
     const WS w = ws_layout(n);
     double *d = wsd(ws);
-    const unsigned lblocks = (unsigned)((w.nleaf + 3) / 4);
+    const uint64_t lblocks = (w.nleaf + 3) / 4;
     if (is_c64)
-        hipLaunchKernelGGL(k_leafsum<float>, dim3(lblocks), dim3(256), 0, s, (const u4 *)psi, n, d + w.off_leafsum);
+        hipLaunchKernelGGL(k_leafsum<float>, grid_for(lblocks), dim3(256), 0, s, (const u4 *)psi, n, d + w.off_leafsum);
     else
-        hipLaunchKernelGGL(k_leafsum<double>, dim3(lblocks), dim3(256), 0, s, (const u4 *)psi, n, d + w.off_leafsum);
+        hipLaunchKernelGGL(k_leafsum<double>, grid_for(lblocks), dim3(256), 0, s, (const u4 *)psi, n, d + w.off_leafsum);
     hipLaunchKernelGGL(k_chunk_total, dim3((unsigned)w.nchunk), dim3(kScanThreads), 0, s, d + w.off_leafsum, w.nleaf,
                        d + w.off_chunk);
     hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kScanThreads), 0, s, d + w.off_chunk, w.nchunk, d + w.off_chunkpre,

@@ -18,6 +18,7 @@
 //     copies the results to pinned host memory; an event marks completion.
 // Every request is validated and deep-copied at submission; results are
 // returned through sv_poll / sv_wait.
+#include "serve_policy.h"
 #include "sv_host.h"
 
 #include <algorithm>
@@ -184,64 +185,54 @@ bool try_admit_large(sv_server s, Req *r) {
     return true;
 }
 
-// Admission under the server lock.
+// Admission under the server lock (policy in serve_policy.h).
 bool admit_locked(sv_server s) {
-    bool progress = false;
-    int scanned = 0;
-    Req *head = s->queue.empty() ? nullptr : s->queue.front();
-    for (auto it = s->queue.begin(); it != s->queue.end() && scanned < 256;) {
-        Req *r = *it;
-        ++scanned;
-        if (r->small) {
-            if ((int)s->pending_small.size() >= 4 * kMaxBatch) {
-                ++it;
-                continue;
-            }
-            r->t_admit = now_ns();
+    if (s->queue.empty()) return false;
+    svp::Limits lim;
+    lim.budget = s->cap;
+    lim.max_large = s->o.max_active;
+    lim.max_small = 4 * kMaxBatch;
+    lim.max_bypass = kMaxBypass;
+    lim.lookahead = 256;
+    const size_t n = std::min<size_t>(s->queue.size(), (size_t)lim.lookahead);
+    std::vector<svp::Candidate> cand(n);
+    for (size_t i = 0; i < n; ++i) {
+        cand[i].small = s->queue[i]->small;
+        cand[i].footprint = s->queue[i]->footprint;
+        cand[i].bypassed = s->queue[i]->bypassed;
+    }
+    auto plan = svp::plan_admission(cand, lim, s->held, (int)s->large.size(), (int)s->pending_small.size(),
+                                    [&](size_t i) { return try_admit_large(s, s->queue[i]); });
+    s->queue[0]->bypassed = cand[0].bypassed;
+    if (plan.empty()) return false;
+    std::vector<char> taken(n, 0);
+    const uint64_t t = now_ns();
+    for (auto &pa : plan) {
+        Req *r = s->queue[pa.first];
+        taken[pa.first] = 1;
+        r->t_admit = t;
+        s->active++;
+        if (pa.second == svp::Action::AdmitSmall) {
             s->pending_small.push_back(r);
-            it = s->queue.erase(it);
-            s->active++;
             s->stats.admitted++;
-            if (head && head != r && head->footprint > 0) head->bypassed++;
-            progress = true;
-            continue;
-        }
-        if (r->footprint > s->cap) {
+        } else if (pa.second == svp::Action::AdmitLarge) {
+            s->large.push_back(r);
+            s->stats.admitted++;
+            s->stats.peak_bytes = std::max<uint64_t>(s->stats.peak_bytes, s->held);
+        } else {
             // can never fit this server's memory
-            it = s->queue.erase(it);
-            s->active++;
             s->stats.rejected++;
-            r->t_admit = now_ns();
             r->status = SV_E_OOM;
-            r->t_done = r->t_admit;
+            r->t_done = t;
             s->done[r->id] = r;
             s->active--;
             s->stats.completed++;
             s->cv.notify_all();
-            progress = true;
-            continue;
         }
-        if ((int)s->large.size() >= s->o.max_active) {
-            // every slot for resident states is taken; small requests may still pass
-            ++it;
-            continue;
-        }
-        if (try_admit_large(s, r)) {
-            r->t_admit = now_ns();
-            s->large.push_back(r);
-            it = s->queue.erase(it);
-            s->active++;
-            s->stats.admitted++;
-            if (head && head != r) head->bypassed++;
-            s->stats.peak_bytes = std::max<uint64_t>(s->stats.peak_bytes, s->held);
-            progress = true;
-            continue;
-        }
-        // did not fit: later (smaller) requests may overtake, within limits
-        if (r == head && r->bypassed >= kMaxBypass) break;
-        ++it;
     }
-    return progress;
+    for (size_t i = n; i-- > 0;)
+        if (taken[i]) s->queue.erase(s->queue.begin() + i);
+    return true;
 }
 
 // ---- packed launches ---------------------------------------------------------------

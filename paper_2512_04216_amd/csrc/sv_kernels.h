@@ -13,6 +13,15 @@ namespace svk {
 // above LB select the segment.
 inline int low_bits(int is_c64) { return is_c64 ? 7 : 6; }
 
+// Launch shape for `blocks` workgroups: one-dimensional up to 2^22 of them,
+// else two-dimensional (x = 2^22); kernels number blocks x-fastest and skip
+// the ids past `blocks`.
+inline dim3 grid_for(uint64_t blocks) {
+    const uint64_t X = 1ull << 22;
+    if (blocks <= X) return dim3((unsigned)(blocks ? blocks : 1));
+    return dim3((unsigned)X, (unsigned)((blocks + X - 1) / X));
+}
+
 // A gate update in "group" form. Each group is a set of 2^K amplitudes whose
 // indices agree with `fv` on the bits of `fm` up to the flip vectors F_j: member
 // m of a group sits at base ^ (XOR of F_j over the set bits j of m), where base
@@ -39,6 +48,9 @@ struct TraceHook;  // per-launch event bracketing (optional)
 hipError_t launch_init(void *psi, int n, int is_c64, uint64_t basis, hipStream_t s);
 hipError_t launch_group(const GroupGate &g, void *psi, int n, int is_c64, hipStream_t s);
 hipError_t launch_diag(const DiagGate &g, void *psi, int n, int is_c64, hipStream_t s);
+// out_dev[2i], out_dev[2i+1] <- re, im of psi[idx_dev[i]] (idx < 2^n checked by the caller)
+hipError_t launch_gather(const void *psi, int is_c64, const uint64_t *idx_dev, int64_t count, double *out_dev,
+                         hipStream_t s);
 // psi <- psi * rsqrt(*norm2_dev)
 hipError_t launch_scale_by_norm(void *psi, int n, int is_c64, const double *norm2_dev,
                                 hipStream_t s);

@@ -36,7 +36,8 @@ class Server:
 
         oa = ops_to_array(ops)
         ta = terms_to_array(terms)
-        c = _abi.sv_circuit(n=int(n), dtype=_dtype_code(dtype), ops=oa, nops=len(ops), fuse_k=int(fuse_k),
+        nops = len(ops)
+        c = _abi.sv_circuit(n=int(n), dtype=_dtype_code(dtype), ops=oa, nops=nops, fuse_k=int(fuse_k),
                             shots=int(shots), seed=int(seed) & (2**64 - 1), terms=ta, nterms=len(terms))
         rid = ctypes.c_uint64()
         check(_lib().sv_submit(self.handle, ctypes.byref(c), ctypes.byref(rid)))

@@ -1,0 +1,117 @@
+// Host-only checks of the request server's admission policy (no GPU, no HIP).
+#include "serve_policy.h"
+
+#include <cstdio>
+#include <cstdlib>
+#include <deque>
+
+using namespace svp;
+
+static int failures = 0;
+#define CHECK(c)                                                        \
+    do {                                                                \
+        if (!(c)) {                                                     \
+            std::printf("FAIL line %d: %s\n", __LINE__, #c);            \
+            ++failures;                                                 \
+        }                                                               \
+    } while (0)
+
+static Candidate large(uint64_t fp) { Candidate c; c.footprint = fp; return c; }
+static Candidate small() { Candidate c; c.small = true; return c; }
+static auto always = [](size_t) { return true; };
+
+int main() {
+    Limits lim;
+    lim.budget = 100;
+    lim.max_large = 8;
+    lim.max_bypass = 3;
+    {   // FIFO: everything fits, admitted in arrival order
+        std::vector<Candidate> q = {large(10), large(10), large(10), small(), large(10)};
+        auto p = plan_admission(q, lim, 0, 0, 0, always);
+        CHECK(p.size() == 5);
+        for (size_t i = 0; i < p.size(); ++i) CHECK(p[i].first == i);
+        CHECK(p[3].second == Action::AdmitSmall && p[4].second == Action::AdmitLarge);
+    }
+    {   // footprint back-pressure: two of 40 fit in 100, the rest wait
+        std::vector<Candidate> q = {large(40), large(40), large(40), large(40)};
+        auto p = plan_admission(q, lim, 0, 0, 0, always);
+        CHECK(p.size() == 2 && p[0].first == 0 && p[1].first == 1);
+    }
+    {   // a request larger than the whole budget is rejected, others proceed
+        std::vector<Candidate> q = {large(200), large(10)};
+        auto p = plan_admission(q, lim, 0, 0, 0, always);
+        CHECK(p.size() == 2 && p[0].second == Action::Reject && p[1].second == Action::AdmitLarge);
+    }
+    {   // resident slots: max_large bounds admissions even with memory free
+        Limits l2 = lim;
+        l2.max_large = 2;
+        std::vector<Candidate> q = {large(1), large(1), large(1), small()};
+        auto p = plan_admission(q, l2, 0, 1, 0, always);
+        CHECK(p.size() == 2 && p[0].first == 0 && p[1].first == 3);
+    }
+    {   // overtaking a blocked head is bounded by max_bypass
+        std::vector<Candidate> q = {large(90), large(5), large(5), small(), large(5), large(5)};
+        auto p = plan_admission(q, lim, 20, 1, 0, always);
+        CHECK(p.size() == 3);            // three overtakes, then admission waits for the head
+        CHECK(q[0].bypassed == 3);
+        auto p2 = plan_admission(q, lim, 20, 1, 0, always);
+        CHECK(p2.empty());               // head still does not fit: nothing behind it moves
+        auto p3 = plan_admission(q, lim, 0, 0, 0, always);
+        CHECK(!p3.empty() && p3[0].first == 0 && p3[0].second == Action::AdmitLarge);
+    }
+    {   // the allocator may refuse (fragmentation): the request waits, nothing is lost
+        std::vector<Candidate> q = {large(10), large(10)};
+        auto p = plan_admission(q, lim, 0, 0, 0, [](size_t i) { return i == 1; });
+        CHECK(p.size() == 1 && p[0].first == 1 && q[0].bypassed == 1);
+    }
+    {   // pending small requests are bounded
+        Limits l2 = lim;
+        l2.max_small = 2;
+        std::vector<Candidate> q = {small(), small(), small()};
+        auto p = plan_admission(q, l2, 0, 0, 1, always);
+        CHECK(p.size() == 1);
+    }
+    {   // lookahead bounds the scan
+        Limits l2 = lim;
+        l2.lookahead = 2;
+        std::vector<Candidate> q = {large(95), large(95), large(1)};
+        auto p = plan_admission(q, l2, 10, 0, 0, always);
+        CHECK(p.empty());
+    }
+    {   // no starvation: a big head under a steady stream of small-footprint
+        // requests is admitted within a bounded number of rounds
+        struct R { Candidate c; int left; };
+        std::deque<R> queue;
+        std::vector<R> resident;
+        queue.push_back({large(80), 3});
+        uint64_t held = 0;
+        int rounds = 0, admitted_big = -1;
+        for (rounds = 0; rounds < 200 && admitted_big < 0; ++rounds) {
+            for (int k = 0; k < 2; ++k) queue.push_back({large(30), 2});
+            std::vector<Candidate> q;
+            for (auto &r : queue) q.push_back(r.c);
+            auto p = plan_admission(q, lim, held, (int)resident.size(), 0, always);
+            queue.front().c.bypassed = q[0].bypassed;
+            std::vector<char> take(q.size(), 0);
+            for (auto &pa : p) {
+                take[pa.first] = 1;
+                if (pa.second == Action::AdmitLarge) {
+                    resident.push_back(queue[pa.first]);
+                    held += queue[pa.first].c.footprint;
+                    if (queue[pa.first].c.footprint == 80) admitted_big = rounds;
+                }
+            }
+            for (size_t i = q.size(); i-- > 0;)
+                if (take[i]) queue.erase(queue.begin() + i);
+            for (size_t i = resident.size(); i-- > 0;)
+                if (--resident[i].left <= 0) {
+                    held -= resident[i].c.footprint;
+                    resident.erase(resident.begin() + i);
+                }
+        }
+        CHECK(admitted_big >= 0 && admitted_big < 20);
+    }
+    if (failures) return 1;
+    std::printf("admission policy: all checks passed\n");
+    return 0;
+}
