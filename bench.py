@@ -134,12 +134,17 @@ def run_28q(S, ctx, dtype, steps, warmup, shots=4096, trace=True):
 
 
 def stream_copy_gbps(nbytes=4 << 30, reps=5):
-    """Achievable HBM bandwidth of a plain device copy (torch), for context."""
+    """Achievable HBM bandwidth of plain device kernels of known size (torch),
+    for context and for calibrating the HBM byte counters: a 4 GiB copy
+    (reads 4 GiB, writes 4 GiB) and an in-place scale of a 4 GiB float tensor
+    (reads and writes the same 4 GiB, the access pattern of a gate sweep)."""
     import torch
 
     a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     b = torch.empty_like(a)
     b.copy_(a)
+    f = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    f.mul_(1.0)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -148,9 +153,15 @@ def stream_copy_gbps(nbytes=4 << 30, reps=5):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
-    del a, b
+    e0.record()
+    for _ in range(reps):
+        f.mul_(1.0)
+    e1.record()
+    torch.cuda.synchronize()
+    ms2 = e0.elapsed_time(e1) / reps
+    del a, b, f
     torch.cuda.empty_cache()
-    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9, 2.0 * nbytes / (ms2 * 1e-3) / 1e9
 
 
 # ---------------------------------------------------------------- other workloads
@@ -335,8 +346,9 @@ def main():
         return
     print("bench: 28-qubit brickwork + QFT, %s, %d warmup + %d timed steps" % (args.dtype, args.warmup, args.steps),
           file=sys.stderr, flush=True)
-    copy_gbps = stream_copy_gbps()
-    print("bench: device copy %.0f GB/s" % copy_gbps, file=sys.stderr, flush=True)
+    copy_gbps, scale_gbps = stream_copy_gbps()
+    print("bench: device copy %.0f GB/s, in-place scale %.0f GB/s" % (copy_gbps, scale_gbps), file=sys.stderr,
+          flush=True)
     ctx = S.Context(arena_bytes=24 << 30)
     r = run_28q(S, ctx, args.dtype, args.steps, args.warmup, trace=not args.no_trace)
     print("bench: %s done in %.3f s" % (args.dtype, r["seconds"]), file=sys.stderr, flush=True)
@@ -373,6 +385,7 @@ def main():
                    "fuse_k": 0, "parallelism": "none (1 GPU)"},
         "hbm_GBps": round(r["algo_bytes"] / r["seconds"] / 1e9, 1),
         "device_copy_GBps": round(copy_gbps, 1),
+        "device_inplace_scale_GBps": round(scale_gbps, 1),
         "roofline": roof,
         "cpu_baseline": cpu,
     }
