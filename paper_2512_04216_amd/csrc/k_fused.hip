@@ -8,12 +8,15 @@
 // with the real embedding
 //     [Re y]   [Ur  -Ui] [Re x]
 //     [Im y] = [Ui   Ur] [Im x]
-// of size D = 2^(k+1). One wavefront owns a tile of 16 columns; its lanes load
-// amplitudes straight into the B-operand layout of V_MFMA_*_16X16X4 (lane l
-// holds B[l/16][l%16]) and store straight from the D layout (lane l holds four
-// rows of column l%16, see drow). The embedded matrix sits in LDS; each
-// instruction reads one A element per lane (A[l%16][l/16]). Double precision
-// uses V_MFMA_F64_16X16X4_F64, single precision V_MFMA_F32_16X16X4_F32.
+// of size 2^(k+1), done as four products per 16x16x4 step: Re y += Ur Re x,
+// Re y += Ui (-Im x), Im y += Ui Re x, Im y += Ur Im x. One wavefront owns a
+// tile of 16 columns; its lanes load amplitudes straight into the B-operand
+// layout of V_MFMA_*_16X16X4 (lane l holds B[l/16][l%16]) and store straight
+// from the accumulator layout (lane l holds four rows of column l%16, see
+// drow). Each lane keeps its A fragments of Ur and Ui (A[l%16][l/16] of every
+// 16x4 block) in registers for the whole launch, and the loads of the next two
+// tiles are in flight while a tile is multiplied. Double precision uses
+// V_MFMA_F64_16X16X4_F64, single precision V_MFMA_F32_16X16X4_F32.
 //
 // k_dense_generic: one thread per column (gather, 2^k x 2^k product, scatter);
 // used for states too small for 16-column tiles.
@@ -58,10 +61,15 @@ struct FArgs {
     uint64_t n_tiles;      // 16-column tiles
     int nhb;               // positions excluded from the tile enumeration (targets + column bits), ascending
     int hb[12];
+    int nruns;             // the free (tile) bit positions as runs: tile bits [off, off+len) go to
+    int run_start[14];     // positions [start, start+len)
+    int run_len[14];
+    int run_off[14];
     int k;
     int targets[5];
     int colbits[4];        // the 4 lowest non-target positions: column index bits
-    T ar[64 * 64];         // real embedding, row-major D x D (only D*D used)
+    T ur[32 * 32];         // Re U, row-major R x R (R = 2^k)
+    T ui[32 * 32];         // Im U
 };
 
 // Bit deposit of the low bits of v into the positions pos[0..cnt).
@@ -71,65 +79,114 @@ __device__ inline uint64_t dep_bits(uint32_t v, const int *pos, int cnt) {
     return o;
 }
 
+// Uniform bit deposit of a wavefront-uniform tile index through the free-bit runs.
+template <typename T>
+__device__ inline uint64_t tile_base(const FArgs<T> &a, uint64_t t) {
+    uint64_t o = 0;
+    for (int j = 0; j < a.nruns; ++j)
+        o |= ((t >> a.run_off[j]) & ((1ull << a.run_len[j]) - 1ull)) << a.run_start[j];
+    return o;
+}
+
 template <typename T, int KK>
 __global__ __launch_bounds__(256) void k_fused_mfma(const FArgs<T> *__restrict__ args, typename CT<T>::amp *__restrict__ psi) {
     constexpr int R = 1 << KK;        // complex rows
-    constexpr int D = 2 * R;          // real rows
-    constexpr int RT = D / 16;        // row tiles
-    constexpr int KS = D / 4;         // k-steps
-    constexpr int KSR = KS / 2;       // k-steps over the real half (amplitude loads per lane)
+    constexpr int H = R / 16;         // 16-row tiles per real / imaginary half
+    constexpr int KSR = R / 4;        // k-steps of 4 complex columns of U (= amplitude loads per lane)
+    constexpr bool F64 = sizeof(T) == 8;
     typedef typename CT<T>::acc ACC;
     typedef typename CT<T>::amp AMP;
-    __shared__ T sA[D * D];
     const FArgs<T> &a = *args;
-    for (int i = threadIdx.x; i < D * D; i += blockDim.x) sA[i] = a.ar[i];
-    __shared__ int s_hb[12], s_t[5], s_c[4];
-    if (threadIdx.x < 12) s_hb[threadIdx.x] = a.hb[threadIdx.x];
-    if (threadIdx.x < 5) s_t[threadIdx.x] = a.targets[threadIdx.x];
-    if (threadIdx.x < 4) s_c[threadIdx.x] = a.colbits[threadIdx.x];
-    __syncthreads();
-    const int nhb = a.nhb;
+    const uint64_t n_tiles = a.n_tiles;
     const int lane = threadIdx.x & 63;
     const int col = lane & 15, g = lane >> 4;
-    const uint64_t coff = dep_bits(col, s_c, 4);
-    // input rows of this lane: m = 4*ks + g, ks < KSR
-    uint64_t roff_in[KSR];
+    // This lane's A fragments for the whole kernel: element (16*h + col, 4*ks + g)
+    // of Re U and Im U. The real embedding [[Ur, -Ui], [Ui, Ur]] only ever needs
+    // these two; -Ui is applied by negating Im x instead.
+    T fr[H][KSR], fi[H][KSR];
 #pragma unroll
-    for (int ks = 0; ks < KSR; ++ks) roff_in[ks] = dep_bits(4 * ks + g, s_t, KK);
-    // output rows of this lane: real row 16*rt + drow(g, v); complex row = that mod R
-    uint64_t roff_out[RT / 2][4];
+    for (int h = 0; h < H; ++h)
 #pragma unroll
-    for (int rt = 0; rt < RT / 2; ++rt)
+        for (int ks = 0; ks < KSR; ++ks) {
+            fr[h][ks] = a.ur[(16 * h + col) * R + 4 * ks + g];
+            fi[h][ks] = a.ui[(16 * h + col) * R + 4 * ks + g];
+        }
+    // Offsets of this lane's rows, split into a lane constant and uniform parts.
+    // Input row of k-step ks: m = 4*ks + g. Output row h, register v: 16*h + drow(g, v),
+    // i.e. g + 4v (FP64 accumulator layout) or 4g + v (FP32).
+    uint64_t tpos[5];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) roff_out[rt][v] = dep_bits(16 * rt + drow((T *)nullptr, g, v), s_t, KK);
+    for (int j = 0; j < KK; ++j) tpos[j] = (uint64_t)a.targets[j];
+    auto bit = [&](int j, int v) { return (uint64_t)(v & 1) << tpos[j]; };
+    const uint64_t coff = dep_bits(col, a.colbits, 4);
+    const uint64_t in_lane = bit(0, g) | bit(1, g >> 1);
+    const uint64_t out_lane = F64 ? in_lane : (bit(2, g) | bit(3, g >> 1));
+    uint64_t in_u[KSR], out_u[H][4];
+#pragma unroll
+    for (int ks = 0; ks < KSR; ++ks) {
+        uint64_t o = 0;
+#pragma unroll
+        for (int j = 2; j < KK; ++j) o |= bit(j, ks >> (j - 2));
+        in_u[ks] = o;
+    }
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            uint64_t o = F64 ? (bit(2, v) | bit(3, v >> 1)) : (bit(0, v) | bit(1, v >> 1));
+            if (KK == 5) o |= bit(4, h);
+            out_u[h][v] = o;
+        }
+    const uint64_t nw = grid_blocks() * (blockDim.x >> 6);
+    uint64_t tile = xcd_block() * (blockDim.x >> 6) + (uint64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
-    const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x >> 6);
-    for (uint64_t tile = wave_id_global(); tile < a.n_tiles; tile += nw) {
-        const uint64_t base = deposit(tile, s_hb, nhb, 0) | coff;
-        AMP x[KSR];
+    // two-deep software pipeline: while a tile is multiplied and stored, the
+    // loads of the next two tiles of this wavefront are in flight
+    auto load = [&](AMP *buf, uint64_t t) {
+        const uint64_t b = tile_base(a, t) | coff | in_lane;
 #pragma unroll
-        for (int ks = 0; ks < KSR; ++ks) x[ks] = psi[base | roff_in[ks]];
-        ACC acc[RT];
+        for (int ks = 0; ks < KSR; ++ks) buf[ks] = psi[b | in_u[ks]];
+    };
+    auto compute_store = [&](const AMP *x, uint64_t t) {
+        const uint64_t base = tile_base(a, t) | coff | out_lane;
+        ACC re[H], im[H];
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) acc[rt] = ACC{0, 0, 0, 0};
+        for (int h = 0; h < H; ++h) {
+            re[h] = ACC{0, 0, 0, 0};
+            im[h] = ACC{0, 0, 0, 0};
+        }
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const T b = ks < KSR ? x[ks].x : x[ks - KSR].y;
+        for (int ks = 0; ks < KSR; ++ks) {
+            const T xr = x[ks].x, xi = x[ks].y, nxi = -x[ks].y;
 #pragma unroll
-            for (int rt = 0; rt < RT; ++rt) {
-                const T av = sA[(16 * rt + col) * D + 4 * ks + g];
-                acc[rt] = mfma(av, b, acc[rt]);
+            for (int h = 0; h < H; ++h) {
+                re[h] = mfma(fr[h][ks], xr, re[h]);    // Re y += Ur Re x
+                re[h] = mfma(fi[h][ks], nxi, re[h]);   //        - Ui Im x
+                im[h] = mfma(fi[h][ks], xr, im[h]);    // Im y += Ui Re x
+                im[h] = mfma(fr[h][ks], xi, im[h]);    //        + Ur Im x
             }
         }
 #pragma unroll
-        for (int rt = 0; rt < RT / 2; ++rt)
+        for (int h = 0; h < H; ++h)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 AMP y;
-                y.x = acc[rt][v];
-                y.y = acc[rt + RT / 2][v];
-                psi[base | roff_out[rt][v]] = y;
+                y.x = re[h][v];
+                y.y = im[h][v];
+                psi[base | out_u[h][v]] = y;
             }
+    };
+    AMP b0[KSR], b1[KSR];
+    if (tile < n_tiles) load(b0, tile);
+    if (tile + nw < n_tiles) load(b1, tile + nw);
+    while (tile < n_tiles) {
+        compute_store(b0, tile);
+        if (tile + 2 * nw < n_tiles) load(b0, tile + 2 * nw);
+        tile += nw;
+        if (tile >= n_tiles) break;
+        compute_store(b1, tile);
+        if (tile + 2 * nw < n_tiles) load(b1, tile + 2 * nw);
+        tile += nw;
     }
 }
 
@@ -206,7 +263,6 @@ hipError_t launch_fused_staged(const double *U, int k, const int *targets, void 
     }
     const int K = 1 << kk;
     if (mfma_ok) {
-        const int D = 2 * K;
         uint64_t tmask = 0;
         for (int j = 0; j < kk; ++j) tmask |= 1ull << tg[j];
         int colbits[4], nc = 0;
@@ -215,22 +271,36 @@ hipError_t launch_fused_staged(const double *U, int k, const int *targets, void 
         uint64_t excl = tmask;
         for (int j = 0; j < 4; ++j) excl |= 1ull << colbits[j];
         auto fill = [&](auto *fa) {
-            using TT = std::remove_reference_t<decltype(fa->ar[0])>;
+            using TT = std::remove_reference_t<decltype(fa->ur[0])>;
             memset(fa, 0, sizeof(*fa));
             fa->n_tiles = 1ull << (n - kk - 4);
             fa->nhb = 0;
             for (int p = 0; p < 64; ++p)
                 if ((excl >> p) & 1) fa->hb[fa->nhb++] = p;
+            // free positions below n as runs of consecutive bits
+            fa->nruns = 0;
+            int off = 0;
+            for (int p = 0; p < n;) {
+                if ((excl >> p) & 1) {
+                    ++p;
+                    continue;
+                }
+                int q = p;
+                while (q < n && !((excl >> q) & 1)) ++q;
+                fa->run_start[fa->nruns] = p;
+                fa->run_len[fa->nruns] = q - p;
+                fa->run_off[fa->nruns] = off;
+                off += q - p;
+                fa->nruns++;
+                p = q;
+            }
             fa->k = kk;
             for (int j = 0; j < kk; ++j) fa->targets[j] = tg[j];
             for (int j = 0; j < 4; ++j) fa->colbits[j] = colbits[j];
             for (int r = 0; r < K; ++r)
                 for (int c = 0; c < K; ++c) {
-                    const double ur = Ue[2 * (r * K + c)], ui = Ue[2 * (r * K + c) + 1];
-                    fa->ar[r * D + c] = (TT)ur;
-                    fa->ar[r * D + K + c] = (TT)(-ui);
-                    fa->ar[(K + r) * D + c] = (TT)ui;
-                    fa->ar[(K + r) * D + K + c] = (TT)ur;
+                    fa->ur[r * K + c] = (TT)Ue[2 * (r * K + c)];
+                    fa->ui[r * K + c] = (TT)Ue[2 * (r * K + c) + 1];
                 }
             return fa->n_tiles;
         };
@@ -245,23 +315,28 @@ hipError_t launch_fused_staged(const double *U, int k, const int *targets, void 
         }
         hipError_t e = hipMemcpyAsync(args_dev, args_host, bytes, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return e;
-        const uint64_t waves = tiles;
-        const uint64_t blocks = std::min<uint64_t>((waves + 3) / 4, 256ull * 8);
+        // one resident wave per tile stream: as many workgroups as the device holds at once
+        auto go = [&](auto kern, auto *fargs, auto *ps) -> hipError_t {
+            static int per_cu[2][2] = {{0, 0}, {0, 0}};
+            int &pc = per_cu[is_c64 ? 1 : 0][kk == 4 ? 0 : 1];
+            if (pc == 0) {
+                int nb = 0;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, 256, 0) != hipSuccess || nb <= 0) nb = 1;
+                pc = nb;
+            }
+            int dev = 0, cus = 256;
+            hipGetDevice(&dev);
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+            const uint64_t blocks = std::min<uint64_t>((tiles + 3) / 4, (uint64_t)cus * pc);
+            hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, s, fargs, ps);
+            return hipGetLastError();
+        };
         if (is_c64) {
-            if (kk == 4)
-                hipLaunchKernelGGL((k_fused_mfma<float, 4>), dim3((unsigned)blocks), dim3(256), 0, s,
-                                   (const FArgs<float> *)args_dev, (float2 *)psi);
-            else
-                hipLaunchKernelGGL((k_fused_mfma<float, 5>), dim3((unsigned)blocks), dim3(256), 0, s,
-                                   (const FArgs<float> *)args_dev, (float2 *)psi);
-        } else {
-            if (kk == 4)
-                hipLaunchKernelGGL((k_fused_mfma<double, 4>), dim3((unsigned)blocks), dim3(256), 0, s,
-                                   (const FArgs<double> *)args_dev, (double2 *)psi);
-            else
-                hipLaunchKernelGGL((k_fused_mfma<double, 5>), dim3((unsigned)blocks), dim3(256), 0, s,
-                                   (const FArgs<double> *)args_dev, (double2 *)psi);
+            if (kk == 4) return go(k_fused_mfma<float, 4>, (const FArgs<float> *)args_dev, (float2 *)psi);
+            return go(k_fused_mfma<float, 5>, (const FArgs<float> *)args_dev, (float2 *)psi);
         }
+        if (kk == 4) return go(k_fused_mfma<double, 4>, (const FArgs<double> *)args_dev, (double2 *)psi);
+        return go(k_fused_mfma<double, 5>, (const FArgs<double> *)args_dev, (double2 *)psi);
         return hipGetLastError();
     }
     // generic path
