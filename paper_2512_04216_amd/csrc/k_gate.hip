@@ -12,6 +12,12 @@
 // ds_bpermute (and from the other half of its own 16-byte slice for complex64).
 // Fixed (control / pattern) bits above LB are skipped by index deposit, so
 // e.g. a controlled gate whose control is a high qubit reads only half the state.
+// Below LB, lanes outside the gate's amplitudes stay idle, except where a
+// member shares a 64-byte run with non-members (a fixed bit that selects runs
+// of 16 or 32 bytes): there the whole run is read and written back, unchanged
+// where not a member, since scattered 16- and 32-byte writes into every line
+// cost more than rewriting it (CX(0,1) at 28 qubits, complex128: 2.09 ms with
+// member-only stores, a full-state sweep takes 1.35 ms).
 #include "sv_device.h"
 #include "sv_kernels.h"
 
@@ -25,6 +31,18 @@ namespace {
 
 constexpr int kBlock = 256;   // 4 wavefronts per workgroup
 constexpr int kSlots = 2;     // outer indices per wavefront (loads in flight)
+
+// Outer indices per wavefront of a group kernel: gates whose members lie in
+// different segments (high flip bits) already load two or four segments per
+// index and stream best with one index per wavefront; the others take two.
+// (28 qubits, complex128: one U3 on qubit 10 at 6.32 vs 6.00 TB/s with one vs
+// two; on qubit 3 at 6.33 vs 6.39 TB/s.)
+template <int KH>
+constexpr int group_slots() { return KH > 0 ? 1 : 2; }
+
+// Index bits (amplitude units) inside one 64-byte run.
+template <typename T>
+constexpr uint32_t run_bits() { return 64 / (2 * sizeof(T)) - 1; }
 
 template <typename T>
 struct GArgs {
@@ -57,13 +75,20 @@ __global__ __launch_bounds__(kBlock) void k_group(GArgs<T> a, u4 *__restrict__ p
     using A = Amp<T>;
     constexpr int E = A::E, LGE = A::LGE, LB = 6 + LGE;
     constexpr int NS = 1 << KH, NL = 1 << KL, M = 1 << (KH + KL);
+    constexpr int SL = group_slots<KH>();
     const int lane = threadIdx.x & 63;
     const uint64_t wave = wave_id_xcd();
 
-    // Which member (if any) each of this lane's amplitudes is, per segment.
+    // Which member (if any) each of this lane's amplitudes is, per segment, and
+    // whether the lane moves its 16 bytes of segment s at all (`part`: it holds
+    // a member, or shares a 64-byte run with one).
+    constexpr uint32_t RUN = run_bits<T>();
     int ml[E];
     bool mem[NS][E];
+    bool part[NS];
     bool lane_valid = (uint32_t)(lane * E) < a.nlow_valid;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) part[s] = false;
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         const uint32_t j = lane * E + r;
@@ -73,13 +98,23 @@ __global__ __launch_bounds__(kBlock) void k_group(GArgs<T> a, u4 *__restrict__ p
         if (KL == 0) {
             ml[r] = 0;
 #pragma unroll
-            for (int s = 0; s < NS; ++s) mem[s][r] = valid && (x == ((MIX && s) ? a.mixlow : 0u));
+            for (int s = 0; s < NS; ++s) {
+                const uint32_t want = (MIX && s) ? a.mixlow : 0u;
+                mem[s][r] = valid && x == want;
+                part[s] = part[s] || (valid && ((x ^ want) & ~RUN) == 0);
+            }
         } else {
+            bool near = false;
 #pragma unroll
-            for (int v = 0; v < NL; ++v)
+            for (int v = 0; v < NL; ++v) {
                 if (x == low_off<T, KL>(a, v)) ml[r] = v;
+                near = near || ((x ^ low_off<T, KL>(a, v)) & ~RUN) == 0;
+            }
 #pragma unroll
-            for (int s = 0; s < NS; ++s) mem[s][r] = valid && ml[r] >= 0;
+            for (int s = 0; s < NS; ++s) {
+                mem[s][r] = valid && ml[r] >= 0;
+                part[s] = part[s] || (valid && near);
+            }
         }
     }
 
@@ -109,33 +144,26 @@ __global__ __launch_bounds__(kBlock) void k_group(GArgs<T> a, u4 *__restrict__ p
     }
 
     // Issue every load of this wavefront's slots before any arithmetic. Lanes
-    // holding no member of any group skip their loads (their amplitudes are
-    // neither changed nor needed as partners).
-    bool need[NS];
+    // that do not take part skip their loads (their amplitudes are neither
+    // changed nor needed as partners).
+    Q v[SL][NS];
+    uint64_t vidx[SL][NS];
+    bool act[SL];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        need[s] = false;
-#pragma unroll
-        for (int r = 0; r < E; ++r) need[s] = need[s] || mem[s][r];
-    }
-    Q v[kSlots][NS];
-    uint64_t vidx[kSlots][NS];
-    bool act[kSlots];
-#pragma unroll
-    for (int sl = 0; sl < kSlots; ++sl) {
-        const uint64_t outer = wave * kSlots + sl;
+    for (int sl = 0; sl < SL; ++sl) {
+        const uint64_t outer = wave * SL + sl;
         act[sl] = outer < a.n_outer;
         const uint64_t base = deposit(act[sl] ? outer : 0, a.hb, a.nhb, LB) | a.fv_high;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             vidx[sl][s] = ((base ^ a.soff[s]) >> LGE) + lane;
             v[sl][s].v = u4{0, 0, 0, 0};
-            if (act[sl] && lane_valid && need[s]) v[sl][s].v = ld_nt(psi + vidx[sl][s]);
+            if (act[sl] && lane_valid && part[s]) v[sl][s].v = ld_nt(psi + vidx[sl][s]);
         }
     }
 
 #pragma unroll
-    for (int sl = 0; sl < kSlots; ++sl) {
+    for (int sl = 0; sl < SL; ++sl) {
         if (!act[sl]) continue;   // wavefront-uniform
         // Partner values from other lanes (all lanes execute the permutes).
         Q sh[NS][NL];
@@ -150,14 +178,9 @@ __global__ __launch_bounds__(kBlock) void k_group(GArgs<T> a, u4 *__restrict__ p
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             Q out = v[sl][s];
-            bool any = false, all = true;
 #pragma unroll
             for (int r = 0; r < E; ++r) {
-                if (!mem[s][r]) {
-                    all = false;
-                    continue;
-                }
-                any = true;
+                if (!mem[s][r]) continue;
                 Cx<T> acc{0, 0};
 #pragma unroll
                 for (int dh = 0; dh < NS; ++dh)
@@ -178,14 +201,7 @@ __global__ __launch_bounds__(kBlock) void k_group(GArgs<T> a, u4 *__restrict__ p
                     }
                 A::set(out, r, acc);
             }
-            if (E == 1 || all) {
-                if (any) st_nt(psi + vidx[sl][s], out.v);
-            } else if (any) {
-                // complex64: only one of the two amplitudes changed
-                uint64_t *p = reinterpret_cast<uint64_t *>(psi + vidx[sl][s]);
-                const int r = mem[s][0] ? 0 : 1;
-                __builtin_nontemporal_store((uint64_t)out.w[2 * r] | ((uint64_t)out.w[2 * r + 1] << 32), p + r);
-            }
+            if (part[s]) st_nt(psi + vidx[sl][s], out.v);
         }
     }
 }
@@ -212,11 +228,14 @@ __global__ __launch_bounds__(kBlock) void k_diag(DArgs<T> a, u4 *__restrict__ ps
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const uint64_t wave = wave_id_xcd();
+    // The lane moves its 16 bytes if they hold a controlled amplitude or share
+    // a 64-byte run with one.
+    constexpr uint32_t RUN = run_bits<T>();
     bool lane_valid = false;
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         const uint32_t j = lane * E + r;
-        lane_valid = lane_valid || (j < a.nlow_valid && (j & a.fm_low) == a.fv_low);
+        lane_valid = lane_valid || (j < a.nlow_valid && (((j & a.fm_low) ^ a.fv_low) & ~RUN) == 0);
     }
     Q v[kSlots];
     uint64_t vidx[kSlots], base[kSlots];
@@ -233,7 +252,6 @@ __global__ __launch_bounds__(kBlock) void k_diag(DArgs<T> a, u4 *__restrict__ ps
 #pragma unroll
     for (int sl = 0; sl < kSlots; ++sl) {
         if (!act[sl] || !lane_valid) continue;
-        bool any = false;
         Q out = v[sl];
 #pragma unroll
         for (int r = 0; r < E; ++r) {
@@ -245,9 +263,8 @@ __global__ __launch_bounds__(kBlock) void k_diag(DArgs<T> a, u4 *__restrict__ ps
             const Cx<T> dm{sd[2 * m], sd[2 * m + 1]};
             Cx<T> acc{0, 0};
             A::set(out, r, cfma(acc, dm, A::get(v[sl], r)));
-            any = true;
         }
-        if (any) st_nt(psi + vidx[sl], out.v);
+        st_nt(psi + vidx[sl], out.v);
     }
 }
 
@@ -324,7 +341,8 @@ void plan_outer(uint64_t fm, uint64_t fv, int n, int LB, uint64_t &n_outer, uint
 
 template <typename T, int KH, int KL, bool MIX>
 hipError_t go_group(const GArgs<T> &a, void *psi, hipStream_t s) {
-    const uint64_t waves = (a.n_outer + kSlots - 1) / kSlots;
+    constexpr int SL = group_slots<KH>();
+    const uint64_t waves = (a.n_outer + SL - 1) / SL;
     const uint64_t blocks = (waves + (kBlock / 64) - 1) / (kBlock / 64);
     hipLaunchKernelGGL((k_group<T, KH, KL, MIX>), svk::grid_for(blocks), dim3(kBlock), 0, s, a, (u4 *)psi);
     return hipGetLastError();
