@@ -75,8 +75,10 @@ typedef struct {
     uint64_t arena_bytes;  /* size of that block in bytes (> 0) */
     void *stream;          /* hipStream_t for new states; NULL: the library creates one
                               at the default priority */
-    int renorm_period;     /* complex64 states: sv_run rescales the state to unit norm
-                              every this many gates and at the end (0: never) */
+    int renorm_period;     /* complex64 states: sv_run (and the server) rescale the state
+                              to unit norm every this many sweeps of the state (one gate,
+                              or one fused block when gates are fused); sv_run also at
+                              its end (0: never). Rounding error builds up per sweep. */
 } sv_ctx_opts;
 
 /* Create a context. opts must not be NULL. */

@@ -132,6 +132,13 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError("libsvsim.so is not built (%s); run paper_2512_04216_amd.build.build()" % path)
+    # torch ships its own HIP runtime under the same soname. Load it first so
+    # the library binds to that one copy: the streams and memory torch hands
+    # over belong to it, and a second runtime in the process finds no device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(path)
     for name, args in PROTOTYPES.items():
         fn = getattr(L, name)

@@ -153,14 +153,18 @@ uint64_t state_bytes(int n, sv_dtype dt) {
     return std::max<uint64_t>(b, 16);
 }
 
-sv_status apply_fused(sv_state st, const cd *U, int k, const int *targets) {
+bool fused_use_mfma(int n, int k) {
     static const bool no_mfma = std::getenv("SV_NO_MFMA") != nullptr;
+    return !no_mfma && n >= 4 + std::max(k, 4);
+}
+
+sv_status apply_fused(sv_state st, const cd *U, int k, const int *targets) {
     sv_ctx c = st->ctx;
     const int slot = c->ring.acquire();
     void *hostp = c->ring.host + (uint64_t)slot * c->ring.slot_bytes;
     void *devp = c->ring.dev + (uint64_t)slot * c->ring.slot_bytes;
     const int s = st->is_c64() ? 8 : 16;
-    const bool mfma = !no_mfma && st->n >= 4 + std::max(k, 4);
+    const bool mfma = fused_use_mfma(st->n, k);
     hipError_t e;
     {
         TraceScope ts(&c->tracer, st->stream, mfma ? "fused_mfma" : "fused_generic", 2.0 * s * std::ldexp(1.0, st->n));
@@ -183,7 +187,7 @@ sv_status renorm(sv_state st) {
     if (r) return r;
     TraceScope ts(&st->ctx->tracer, st->stream, "scale", 2.0 * st->bytes);
     SV_HIP(svk::launch_scale_by_norm(st->psi, st->n, st->is_c64(), svk::norm2_dev_ptr(st->ws, st->n), st->stream));
-    st->gates_since_renorm = 0;
+    st->sweeps_since_renorm = 0;
     return SV_OK;
 }
 
@@ -375,7 +379,7 @@ sv_status sv_reset(sv_state st, uint64_t basis) {
     if (basis >= (1ull << st->n)) return fail(SV_E_INVALID, "basis index >= 2^n");
     TraceScope ts(&st->ctx->tracer, st->stream, "init", (double)st->bytes);
     SV_HIP(svk::launch_init(st->psi, st->n, st->is_c64(), basis, st->stream));
-    st->gates_since_renorm = 0;
+    st->sweeps_since_renorm = 0;
     return SV_OK;
 }
 
@@ -498,10 +502,10 @@ sv_status sv_run(sv_state st, const sv_op *ops, int nops, int fuse_k) {
     sv_status r = validate_ops(st, ops, nops);
     if (r) return r;
     const int R = st->is_c64() ? st->ctx->renorm_period : 0;
-    auto after = [&](int gates) -> sv_status {
+    auto after = [&](int sweeps) -> sv_status {
         if (R <= 0) return SV_OK;
-        st->gates_since_renorm += gates;
-        if (st->gates_since_renorm >= R) return renorm(st);
+        st->sweeps_since_renorm += sweeps;
+        if (st->sweeps_since_renorm >= R) return renorm(st);
         return SV_OK;
     };
     if (fuse_k == 0 || std::min(fuse_k, st->n) < 2) {
@@ -525,11 +529,11 @@ sv_status sv_run(sv_state st, const sv_op *ops, int nops, int fuse_k) {
                 else r = apply_fused(st, U.data(), k, b.qubits.data());
             }
             if (r) return r;
-            r = after((int)b.ops.size());
+            r = after(1);
             if (r) return r;
         }
     }
-    if (R > 0 && st->gates_since_renorm > 0) return renorm(st);
+    if (R > 0 && st->sweeps_since_renorm > 0) return renorm(st);
     return SV_OK;
 }
 

@@ -296,50 +296,90 @@ std::vector<Block> plan_fusion(const sv_op *ops, int nops, int fuse_k) {
     return out;
 }
 
-// Block matrix: apply every gate of the block to each basis column of the
-// 2^k identity (a tiny state-vector pass on the host, complex128).
+// Block matrix: U = G_last ... G_first on the block's qubits, built by applying
+// each gate to the rows of a K x K matrix that starts as the identity
+// (complex128, real and imaginary parts in separate row-major arrays so the
+// row updates vectorise). Every gate's matrix is built once. Diagonal gates
+// scale rows and 0/1 permutations move them; other gates mix their rows.
 void block_matrix(const sv_op *ops, const Block &b, std::vector<cd> &U) {
     const int k = (int)b.qubits.size();
     const int K = 1 << k;
     int pos[64];
     for (int j = 0; j < k; ++j) pos[b.qubits[j]] = j;
-    U.assign((size_t)K * K, 0.0);
-    std::vector<cd> col(K);
-    for (int c = 0; c < K; ++c) {
-        std::fill(col.begin(), col.end(), cd(0.0));
-        col[c] = 1.0;
-        for (int oi : b.ops) {
-            const sv_op &o = ops[oi];
-            cd G[16];
-            int gk, nc;
-            gate_matrix(o.kind, o.p, o.flags & SV_OP_ADJOINT, G, &gk, &nc);
-            const int GK = 1 << gk;
-            int tg[3], cl[3];
-            for (int j = 0; j < nc; ++j) cl[j] = pos[o.q[j]];
-            for (int j = 0; j < gk; ++j) tg[j] = pos[o.q[nc + j]];
-            uint64_t tm = 0, cm = 0;
-            for (int j = 0; j < gk; ++j) tm |= 1ull << tg[j];
-            for (int j = 0; j < nc; ++j) cm |= 1ull << cl[j];
-            for (int i = 0; i < K; ++i) {
-                if ((i & tm) || (i & cm) != cm) continue;
-                cd v[4];
-                int idx[4];
-                for (int m = 0; m < GK; ++m) {
-                    int a = i;
-                    for (int j = 0; j < gk; ++j)
-                        if ((m >> j) & 1) a |= 1 << tg[j];
-                    idx[m] = a;
-                    v[m] = col[a];
-                }
+    std::vector<double> re((size_t)K * K, 0.0), im((size_t)K * K, 0.0), tr(4 * K), ti(4 * K);
+    for (int r = 0; r < K; ++r) re[(size_t)r * K + r] = 1.0;
+    for (int oi : b.ops) {
+        const sv_op &o = ops[oi];
+        cd G[16];
+        int gk, nc;
+        gate_matrix(o.kind, o.p, o.flags & SV_OP_ADJOINT, G, &gk, &nc);
+        const int GK = 1 << gk;
+        int tg[3];
+        uint64_t tm = 0, cm = 0;
+        for (int j = 0; j < nc; ++j) cm |= 1ull << pos[o.q[j]];
+        for (int j = 0; j < gk; ++j) {
+            tg[j] = pos[o.q[nc + j]];
+            tm |= 1ull << tg[j];
+        }
+        bool diag = true, perm = true;
+        for (int r = 0; r < GK; ++r)
+            for (int m = 0; m < GK; ++m) {
+                const cd g = G[r * GK + m];
+                if (r != m && g != 0.0) diag = false;
+                if (g != 0.0 && g != 1.0) perm = false;
+            }
+        for (int i = 0; i < K; ++i) {
+            if ((i & tm) || (i & cm) != cm) continue;
+            int idx[4];
+            for (int m = 0; m < GK; ++m) {
+                int a = i;
+                for (int j = 0; j < gk; ++j)
+                    if ((m >> j) & 1) a |= 1 << tg[j];
+                idx[m] = a;
+            }
+            if (diag) {
                 for (int r = 0; r < GK; ++r) {
-                    cd w = 0.0;
-                    for (int m = 0; m < GK; ++m) w += G[r * GK + m] * v[m];
-                    col[idx[r]] = w;
+                    const double gr = G[r * GK + r].real(), gi = G[r * GK + r].imag();
+                    if (gr == 1.0 && gi == 0.0) continue;
+                    double *xr = &re[(size_t)idx[r] * K], *xi = &im[(size_t)idx[r] * K];
+                    for (int c = 0; c < K; ++c) {
+                        const double a = xr[c], bb = xi[c];
+                        xr[c] = gr * a - gi * bb;
+                        xi[c] = gr * bb + gi * a;
+                    }
+                }
+                continue;
+            }
+            // keep the gate's input rows, then write its output rows
+            for (int m = 0; m < GK; ++m) {
+                std::copy_n(&re[(size_t)idx[m] * K], K, &tr[(size_t)m * K]);
+                std::copy_n(&im[(size_t)idx[m] * K], K, &ti[(size_t)m * K]);
+            }
+            for (int r = 0; r < GK; ++r) {
+                double *yr = &re[(size_t)idx[r] * K], *yi = &im[(size_t)idx[r] * K];
+                if (perm) {
+                    int m = 0;
+                    while (G[r * GK + m] == 0.0) ++m;
+                    std::copy_n(&tr[(size_t)m * K], K, yr);
+                    std::copy_n(&ti[(size_t)m * K], K, yi);
+                    continue;
+                }
+                std::fill_n(yr, K, 0.0);
+                std::fill_n(yi, K, 0.0);
+                for (int m = 0; m < GK; ++m) {
+                    const double gr = G[r * GK + m].real(), gi = G[r * GK + m].imag();
+                    if (gr == 0.0 && gi == 0.0) continue;
+                    const double *xr = &tr[(size_t)m * K], *xi = &ti[(size_t)m * K];
+                    for (int c = 0; c < K; ++c) {
+                        yr[c] += gr * xr[c] - gi * xi[c];
+                        yi[c] += gr * xi[c] + gi * xr[c];
+                    }
                 }
             }
         }
-        for (int r = 0; r < K; ++r) U[(size_t)r * K + c] = col[r];
     }
+    U.resize((size_t)K * K);
+    for (size_t e = 0; e < (size_t)K * K; ++e) U[e] = cd(re[e], im[e]);
 }
 
 }  // namespace svh

@@ -24,6 +24,7 @@
 #include "sv_kernels.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <type_traits>
 
@@ -228,12 +229,15 @@ __global__ __launch_bounds__(256) void k_dense_generic(const GDArgs<T> *__restri
 namespace svk {
 
 // Kernel argument blocks for the fused kernels are too large for the kernarg
-// segment (up to 32 KiB), so they are staged in a small device buffer owned by
-// the caller's workspace (see fused_args_bytes).
+// segment (up to 32 KiB), so they are staged in device memory the caller owns
+// (fused_args_bytes per block).
 uint64_t fused_args_bytes() { return std::max(sizeof(FArgs<double>), sizeof(GDArgs<double>)); }
+uint64_t fused_args_bytes_dt(int is_c64) {
+    return is_c64 ? std::max(sizeof(FArgs<float>), sizeof(GDArgs<float>)) : fused_args_bytes();
+}
 
-hipError_t launch_fused_staged(const double *U, int k, const int *targets, void *psi, int n, int is_c64,
-                               hipStream_t s, int use_mfma, void *args_dev, void *args_host) {
+hipError_t fused_prepare(const double *U, int k, const int *targets, int n, int is_c64, int use_mfma, void *args_host,
+                         FusedLaunch *out) {
     // column-major choice: MFMA tiles need n >= k + 4
     int kk = k;
     int tg[5];
@@ -262,6 +266,8 @@ hipError_t launch_fused_staged(const double *U, int k, const int *targets, void 
             }
     }
     const int K = 1 << kk;
+    out->is_c64 = is_c64;
+    out->kk = kk;
     if (mfma_ok) {
         uint64_t tmask = 0;
         for (int j = 0; j < kk; ++j) tmask |= 1ull << tg[j];
@@ -304,40 +310,15 @@ hipError_t launch_fused_staged(const double *U, int k, const int *targets, void 
                 }
             return fa->n_tiles;
         };
-        uint64_t tiles;
-        size_t bytes;
+        out->kind = 0;
         if (is_c64) {
-            tiles = fill((FArgs<float> *)args_host);
-            bytes = sizeof(FArgs<float>);
+            out->work = fill((FArgs<float> *)args_host);
+            out->bytes = sizeof(FArgs<float>);
         } else {
-            tiles = fill((FArgs<double> *)args_host);
-            bytes = sizeof(FArgs<double>);
+            out->work = fill((FArgs<double> *)args_host);
+            out->bytes = sizeof(FArgs<double>);
         }
-        hipError_t e = hipMemcpyAsync(args_dev, args_host, bytes, hipMemcpyHostToDevice, s);
-        if (e != hipSuccess) return e;
-        // one resident wave per tile stream: as many workgroups as the device holds at once
-        auto go = [&](auto kern, auto *fargs, auto *ps) -> hipError_t {
-            static int per_cu[2][2] = {{0, 0}, {0, 0}};
-            int &pc = per_cu[is_c64 ? 1 : 0][kk == 4 ? 0 : 1];
-            if (pc == 0) {
-                int nb = 0;
-                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, 256, 0) != hipSuccess || nb <= 0) nb = 1;
-                pc = nb;
-            }
-            int dev = 0, cus = 256;
-            hipGetDevice(&dev);
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-            const uint64_t blocks = std::min<uint64_t>((tiles + 3) / 4, (uint64_t)cus * pc);
-            hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, s, fargs, ps);
-            return hipGetLastError();
-        };
-        if (is_c64) {
-            if (kk == 4) return go(k_fused_mfma<float, 4>, (const FArgs<float> *)args_dev, (float2 *)psi);
-            return go(k_fused_mfma<float, 5>, (const FArgs<float> *)args_dev, (float2 *)psi);
-        }
-        if (kk == 4) return go(k_fused_mfma<double, 4>, (const FArgs<double> *)args_dev, (double2 *)psi);
-        return go(k_fused_mfma<double, 5>, (const FArgs<double> *)args_dev, (double2 *)psi);
-        return hipGetLastError();
+        return hipSuccess;
     }
     // generic path
     auto fillg = [&](auto *ga) {
@@ -356,25 +337,78 @@ hipError_t launch_fused_staged(const double *U, int k, const int *targets, void 
         for (int i = 0; i < 2 * K * K; ++i) ga->u[i] = (TT)Ue[i];
         return ga->ncols;
     };
-    uint64_t cols;
-    size_t bytes;
+    out->kind = 1;
     if (is_c64) {
-        cols = fillg((GDArgs<float> *)args_host);
-        bytes = sizeof(GDArgs<float>);
+        out->work = fillg((GDArgs<float> *)args_host);
+        out->bytes = sizeof(GDArgs<float>);
     } else {
-        cols = fillg((GDArgs<double> *)args_host);
-        bytes = sizeof(GDArgs<double>);
+        out->work = fillg((GDArgs<double> *)args_host);
+        out->bytes = sizeof(GDArgs<double>);
     }
-    hipError_t e = hipMemcpyAsync(args_dev, args_host, bytes, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return e;
-    const uint64_t blocks = std::min<uint64_t>((cols + 255) / 256, 256ull * 16);
-    if (is_c64)
+    return hipSuccess;
+}
+
+namespace {
+
+// Compute units and resident 256-thread workgroups per CU of each MFMA kernel,
+// per device, looked up once.
+constexpr int kMaxDevices = 64;
+std::atomic<int> g_cus[kMaxDevices];
+std::atomic<int> g_per_cu[kMaxDevices][4];
+
+template <typename K>
+uint64_t resident_blocks(K kern, int slot) {
+    int dev = 0;
+    hipGetDevice(&dev);
+    if (dev < 0 || dev >= kMaxDevices) dev = 0;
+    int cus = g_cus[dev].load(std::memory_order_relaxed);
+    if (cus <= 0) {
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+        g_cus[dev].store(cus, std::memory_order_relaxed);
+    }
+    int pc = g_per_cu[dev][slot].load(std::memory_order_relaxed);
+    if (pc <= 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, kern, 256, 0) != hipSuccess || pc <= 0) pc = 1;
+        g_per_cu[dev][slot].store(pc, std::memory_order_relaxed);
+    }
+    return (uint64_t)cus * (uint64_t)pc;
+}
+
+}  // namespace
+
+hipError_t fused_launch(const FusedLaunch &f, const void *args_dev, void *psi, hipStream_t s) {
+    if (f.kind == 0) {
+        // one resident wave per tile stream: as many workgroups as the device holds at once
+        auto go = [&](auto kern, int slot, auto *fargs, auto *ps) -> hipError_t {
+            const uint64_t blocks = std::min<uint64_t>((f.work + 3) / 4, resident_blocks(kern, slot));
+            hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, s, fargs, ps);
+            return hipGetLastError();
+        };
+        if (f.is_c64) {
+            if (f.kk == 4) return go(k_fused_mfma<float, 4>, 0, (const FArgs<float> *)args_dev, (float2 *)psi);
+            return go(k_fused_mfma<float, 5>, 1, (const FArgs<float> *)args_dev, (float2 *)psi);
+        }
+        if (f.kk == 4) return go(k_fused_mfma<double, 4>, 2, (const FArgs<double> *)args_dev, (double2 *)psi);
+        return go(k_fused_mfma<double, 5>, 3, (const FArgs<double> *)args_dev, (double2 *)psi);
+    }
+    const uint64_t blocks = std::min<uint64_t>((f.work + 255) / 256, 256ull * 16);
+    if (f.is_c64)
         hipLaunchKernelGGL(k_dense_generic<float>, dim3((unsigned)blocks), dim3(256), 0, s,
                            (const GDArgs<float> *)args_dev, (float2 *)psi);
     else
         hipLaunchKernelGGL(k_dense_generic<double>, dim3((unsigned)blocks), dim3(256), 0, s,
                            (const GDArgs<double> *)args_dev, (double2 *)psi);
     return hipGetLastError();
+}
+
+hipError_t launch_fused_staged(const double *U, int k, const int *targets, void *psi, int n, int is_c64,
+                               hipStream_t s, int use_mfma, void *args_dev, void *args_host) {
+    FusedLaunch f;
+    hipError_t e = fused_prepare(U, k, targets, n, is_c64, use_mfma, args_host, &f);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(args_dev, args_host, f.bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    return fused_launch(f, args_dev, psi, s);
 }
 
 }  // namespace svk

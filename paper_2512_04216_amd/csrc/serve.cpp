@@ -68,6 +68,17 @@ struct Req {
     sv_state st = nullptr;
     int stream_idx = 0;
     std::vector<Block> blocks;
+    // Blocks are prepared once, on the request's first pass: a kind per block
+    // (0 one op, 1 matrix on <= 2 qubits, 2 fused kernel), the kind-1
+    // matrices, and the kind-2 kernel argument blocks, copied to the device in
+    // one transfer.
+    bool prepared = false;
+    std::vector<uint8_t> bkind;
+    std::vector<uint32_t> bref;              // index into smallU (x16) or fl
+    std::vector<cd> smallU;
+    std::vector<svk::FusedLaunch> fl;
+    char *ahost = nullptr, *adev = nullptr;  // argument blocks (pinned / device)
+    uint64_t astride = 0;
     size_t next = 0, total = 0;
     bool measuring = false;
     hipEvent_t ev = nullptr;
@@ -146,6 +157,9 @@ void release_large(sv_server s, Req *r) {
     r->dbuf = nullptr;
     if (r->hbuf) s->pinned.free(r->hbuf);
     r->hbuf = nullptr;
+    if (r->adev) s->ctx->arena.free(r->adev);
+    if (r->ahost) s->pinned.free(r->ahost);
+    r->adev = r->ahost = nullptr;
     s->held -= r->footprint;
 }
 
@@ -182,6 +196,61 @@ bool try_admit_large(sv_server s, Req *r) {
     }
     r->next = 0;
     r->measuring = false;
+    r->prepared = r->fuse_k < 2;
+    return true;
+}
+
+// Block kinds, small matrices and fused argument blocks of a fused request
+// (driver thread, outside the server lock). false: no memory for the argument
+// blocks right now; the request stays admitted and is prepared later.
+bool prepare_blocks(sv_server s, Req *r) {
+    const int nb = (int)r->blocks.size();
+    const int is_c64 = r->st->is_c64() ? 1 : 0;
+    int nf = 0;
+    for (const Block &b : r->blocks)
+        if (b.ops.size() > 1 && b.qubits.size() > 2) ++nf;
+    r->astride = (svk::fused_args_bytes_dt(is_c64) + 255) & ~255ull;
+    if (nf > 0) {
+        r->ahost = (char *)s->pinned.alloc(nf * r->astride);
+        r->adev = r->ahost ? (char *)s->ctx->arena.alloc(nf * r->astride) : nullptr;
+        if (!r->ahost || !r->adev) {
+            if (r->ahost) s->pinned.free(r->ahost);
+            r->ahost = nullptr;
+            return false;
+        }
+    }
+    r->bkind.assign(nb, 0);
+    r->bref.assign(nb, 0);
+    r->smallU.clear();
+    r->fl.assign(nf, svk::FusedLaunch{});
+    std::vector<cd> U;
+    int f = 0;
+    for (int j = 0; j < nb; ++j) {
+        const Block &b = r->blocks[j];
+        if (b.ops.size() == 1) continue;
+        block_matrix(r->ops.data(), b, U);
+        const int k = (int)b.qubits.size();
+        if (k <= 2) {
+            r->bkind[j] = 1;
+            r->bref[j] = (uint32_t)(r->smallU.size() / 16);
+            U.resize(16);
+            r->smallU.insert(r->smallU.end(), U.begin(), U.end());
+        } else {
+            r->bkind[j] = 2;
+            r->bref[j] = (uint32_t)f;
+            svk::fused_prepare(reinterpret_cast<const double *>(U.data()), k, b.qubits.data(), r->n, is_c64,
+                               fused_use_mfma(r->n, k) ? 1 : 0, r->ahost + f * r->astride, &r->fl[f]);
+            ++f;
+        }
+    }
+    if (nf > 0 &&
+        hipMemcpyAsync(r->adev, r->ahost, nf * r->astride, hipMemcpyHostToDevice, r->st->stream) != hipSuccess) {
+        s->ctx->arena.free(r->adev);
+        s->pinned.free(r->ahost);
+        r->adev = r->ahost = nullptr;
+        return false;
+    }
+    r->prepared = true;
     return true;
 }
 
@@ -380,10 +449,9 @@ bool launch_small(sv_server s) {
 sv_status enqueue_measure(sv_server s, Req *r) {
     sv_state st = r->st;
     const hipStream_t str = st->stream;
-    if (st->is_c64() && s->ctx->renorm_period > 0 && st->gates_since_renorm > 0) {
-        sv_status q = renorm(st);
-        if (q) return q;
-    }
+    // No final rescale: the sampler draws against the FP64 total of the CDF
+    // and every expectation is divided by the FP64 norm, and the state is
+    // dropped after measuring.
     uint64_t *dsamp = (uint64_t *)r->dbuf;
     double *dres = (double *)(r->dbuf + 8 * r->shots);
     const uint64_t nres = (uint64_t)std::max(1, r->nzb) * (kTB + 1) + 2ull * r->xi.size() + 1;
@@ -429,31 +497,32 @@ bool advance_large(sv_server s) {
     for (Req *r : s->large) {
         if (r->measuring) continue;
         const int R = r->st->is_c64() ? s->ctx->renorm_period : 0;
+        if (!r->prepared && !prepare_blocks(s, r)) continue;
         int budget = kChunk;
         sv_status q = SV_OK;
-        std::vector<cd> U;
         while (budget > 0 && r->next < r->total && q == SV_OK) {
-            int absorbed = 1;
             if (r->fuse_k >= 2) {
-                const Block &b = r->blocks[r->next];
-                absorbed = (int)b.ops.size();
-                if (b.ops.size() == 1) {
+                const size_t j = r->next;
+                const Block &b = r->blocks[j];
+                if (r->bkind[j] == 0) {
                     q = apply_op(r->st, r->ops[b.ops[0]]);
+                } else if (r->bkind[j] == 1) {
+                    q = apply_matrix(r->st, r->smallU.data() + 16 * r->bref[j], (int)b.qubits.size(),
+                                     b.qubits.data(), nullptr, 0);
                 } else {
-                    block_matrix(r->ops.data(), b, U);
-                    const int k = (int)b.qubits.size();
-                    q = k <= 2 ? apply_matrix(r->st, U.data(), k, b.qubits.data(), nullptr, 0)
-                               : apply_fused(r->st, U.data(), k, b.qubits.data());
+                    const svk::FusedLaunch &f = r->fl[r->bref[j]];
+                    TraceScope ts(&s->ctx->tracer, r->st->stream, f.kind == 0 ? "fused_mfma" : "fused_generic",
+                                  2.0 * (double)r->st->bytes);
+                    const hipError_t e =
+                        svk::fused_launch(f, r->adev + r->bref[j] * r->astride, r->st->psi, r->st->stream);
+                    if (e != hipSuccess) q = hip_fail(e, "fused block launch");
                 }
             } else {
                 q = apply_op(r->st, r->ops[r->next]);
             }
             r->next++;
             --budget;
-            if (q == SV_OK && R > 0) {
-                r->st->gates_since_renorm += absorbed;
-                if (r->st->gates_since_renorm >= R) q = renorm(r->st);
-            }
+            if (q == SV_OK && R > 0 && ++r->st->sweeps_since_renorm >= R) q = renorm(r->st);
         }
         if (q == SV_OK && r->next == r->total) {
             q = enqueue_measure(s, r);

@@ -118,7 +118,7 @@ struct sv_state_s {
     void *ws = nullptr;         // measurement workspace (device)
     uint64_t ws_bytes = 0;
     hipStream_t stream = nullptr;
-    int gates_since_renorm = 0;
+    int sweeps_since_renorm = 0;   // gates or fused blocks applied since the last rescale
     bool is_c64() const { return dtype == SV_C64; }
 };
 
@@ -146,6 +146,8 @@ sv_status apply_op(sv_state st, const sv_op &o);
 sv_status apply_matrix(sv_state st, const cd *U, int k, const int *targets, const int *controls, int nc);
 // dense block via the fused kernels
 sv_status apply_fused(sv_state st, const cd *U, int k, const int *targets);
+// whether a k-qubit block on n qubits runs on the MFMA kernel (SV_NO_MFMA set: never)
+bool fused_use_mfma(int n, int k);
 
 // fusion planning
 struct Block {

@@ -56,10 +56,23 @@ hipError_t launch_scale_by_norm(void *psi, int n, int is_c64, const double *norm
                                 hipStream_t s);
 
 // Dense k-qubit block (k <= 5) on arbitrary targets; U row-major complex128.
-// The kernel argument block (fused_args_bytes) is written to args_host (pinned)
-// and copied to args_dev on stream s; both must stay untouched until the
-// launch has run.
-uint64_t fused_args_bytes();
+// A block's kernel argument block (at most fused_args_bytes) lives in device
+// memory: fused_prepare fills it in host memory (no HIP call), the caller
+// copies it to the device, and fused_launch runs the block from there.
+// launch_fused_staged does all three, with args_host pinned and both buffers
+// left untouched until the launch has run.
+struct FusedLaunch {
+    int kind = 0;        // 0: MFMA tiles, 1: one thread per column
+    int kk = 0;          // block width the kernel runs (blocks of 3 run padded to 4)
+    int is_c64 = 0;
+    uint64_t work = 0;   // 16-column tiles (kind 0) or columns (kind 1)
+    uint64_t bytes = 0;  // bytes of the argument block to copy
+};
+uint64_t fused_args_bytes();                 // either dtype
+uint64_t fused_args_bytes_dt(int is_c64);    // one dtype
+hipError_t fused_prepare(const double *U, int k, const int *targets, int n, int is_c64, int use_mfma,
+                         void *args_host, FusedLaunch *out);
+hipError_t fused_launch(const FusedLaunch &f, const void *args_dev, void *psi, hipStream_t s);
 hipError_t launch_fused_staged(const double *U, int k, const int *targets, void *psi, int n,
                                int is_c64, hipStream_t s, int use_mfma, void *args_dev,
                                void *args_host);
