@@ -225,7 +225,7 @@ typedef struct {
     int small_qubits;       /* requests with n <= this run in the packed persistent
                                kernel (0: 13 for complex64, 12 for complex128) */
     int max_queue;          /* most queued requests before sv_submit returns SV_E_BUSY (0: 1<<20) */
-    int nstreams;           /* HIP streams the driver spreads large requests over (0: 4) */
+    int nstreams;           /* HIP streams the driver spreads large requests over (0: 3) */
 } sv_server_opts;
 
 typedef struct {

@@ -62,6 +62,25 @@ def test_serving_matches_oracle(ctx, S, O):
         assert res["t_submit_ns"] <= res["t_admit_ns"] <= res["t_done_ns"]
 
 
+def test_serving_stream_spot_checks(ctx, S, O):
+    # 240 requests of the serving recipe (complex64, fused blocks of <= 5
+    # qubits, 1000 shots), qubit counts 8..18 so the oracle finishes quickly:
+    # packed small circuits and resident states in one mix.
+    reqs = W.serving_stream(240, seed=20251211, n_lo=8, n_hi=18)
+    for i, r in enumerate(reqs):
+        n = r["n"]
+        r["terms"] = [(0, 0b11 << (i % (n - 1)), 1.0), (1 << (i % n), 0, 0.5)]
+        r["dtype"], r["fuse_k"] = "c64", 5
+    with S.Server(ctx) as srv:
+        ids = [_submit(srv, r) for r in reqs]
+        results = [srv.wait(i, 120000) for i in ids]
+        st = srv.stats()
+    assert st["completed"] == len(reqs) and st["packed_circuits"] > 0 and st["packed_circuits"] < len(reqs)
+    for r, res in zip(reqs, results):
+        assert res is not None
+        _check_vs_oracle(O, r, res)
+
+
 def test_alone_equals_mix_bitwise(ctx, S):
     reqs = _requests(2, 48, 4, 20, fuse=(0, 5))
     with S.Server(ctx) as srv:
