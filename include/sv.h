@@ -152,19 +152,33 @@ typedef struct {
 sv_status sv_gate_matrix(int kind, const double *params, int adjoint, double *U_out,
                          int *k_out, int *ncontrols_out);
 
-/* Run a gate list in order. fuse_k = 0 launches one kernel per gate; 2..5 first
- * groups the gates greedily into blocks of at most fuse_k qubits (a gate joins
- * the open block(s) sharing its qubits while their union stays within fuse_k;
- * the block matrix is the product of the embedded gate matrices, formed in
- * complex128 on the host) and applies each block of 3 or more qubits with
- * sv_apply_fused's kernels (MFMA). With fuse_k > 0 the order of gates on
- * disjoint qubits may change; the result is the same up to rounding. */
+/* sv_run / sv_circuit fuse_k value: multi-gate passes over LDS tiles. */
+#define SV_FUSE_TILED (-1)
+
+/* Run a gate list in order (the state-vector method, Sec. II: one update of
+ * the amplitude vector per gate). fuse_k = 0 launches one kernel per gate;
+ * 2..5 first groups the gates greedily into blocks of at most fuse_k qubits (a
+ * gate joins the open block(s) sharing its qubits while their union stays
+ * within fuse_k; the block matrix is the product of the embedded gate
+ * matrices, formed in complex128 on the host) and applies each block of 3 or
+ * more qubits with sv_apply_fused's kernels (MFMA). SV_FUSE_TILED plans passes
+ * instead: each pass keeps tiles of 2^13 (complex128) or 2^14 (complex64)
+ * amplitudes in LDS, spanning the lowest 6 / 7 qubits and up to 7 chosen
+ * others, and applies every gate whose mixed qubits are tile qubits
+ * (controls and diagonal factors may sit on any qubit) in one read and write
+ * of the state; the gate records are staged in the context's arena. With
+ * fuse_k != 0 the order of gates on disjoint qubits may change; the result is
+ * the same up to rounding. */
 sv_status sv_run(sv_state st, const sv_op *ops, int nops, int fuse_k);
 
 /* Fusion plan of a gate list without running it: number of blocks and of ops
  * left unfused. */
 sv_status sv_plan_fusion(const sv_op *ops, int nops, int n, int fuse_k, int *nblocks,
                          int *nsingle);
+
+/* Tiled-pass plan of a gate list on n qubits of type dt without running it:
+ * the number of passes (each one read and write of the state). */
+sv_status sv_plan_passes(const sv_op *ops, int nops, int n, sv_dtype dt, int *npasses);
 
 /* --------------------------------------------------------- measurement */
 

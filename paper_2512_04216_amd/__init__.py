@@ -15,11 +15,11 @@ import numpy as np
 
 from . import _abi
 from ._abi import (  # noqa: F401
-    GATE_KIND, GATE_KINDS, SV_C64, SV_C128, SV_OP_ADJOINT, SvError, check, load, sv_op, sv_pauli,
+    GATE_KIND, GATE_KINDS, SV_C64, SV_C128, SV_FUSE_TILED, SV_OP_ADJOINT, SvError, check, load, sv_op, sv_pauli,
 )
 
 __all__ = ["Context", "State", "Server", "ops_to_array", "terms_to_array", "SvError", "load",
-           "GATE_KIND", "SV_C64", "SV_C128"]
+           "GATE_KIND", "SV_C64", "SV_C128", "SV_FUSE_TILED"]
 
 
 def lib():
@@ -93,6 +93,14 @@ def sv_gate_matrix(kind, params=(), adjoint=False):
                                ctypes.byref(k), ctypes.byref(nc)))
     K = 1 << k.value
     return U[: K * K].reshape(K, K).copy(), k.value, nc.value
+
+
+def sv_plan_passes(ops, n, dtype="c128"):
+    """Number of tiled passes sv_run(..., SV_FUSE_TILED) makes for this gate list."""
+    arr = ops_to_array(ops)
+    npass = ctypes.c_int()
+    check(lib().sv_plan_passes(arr, len(ops), n, _dtype_code(dtype), ctypes.byref(npass)))
+    return npass.value
 
 
 def sv_plan_fusion(ops, n, fuse_k):

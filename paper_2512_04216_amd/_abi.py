@@ -17,6 +17,7 @@ SV_E_NOTFOUND, SV_E_BUSY, SV_E_UNSUPPORTED = -5, -6, -7
 SV_C64, SV_C128 = 0, 1
 SV_OP_ADJOINT = 1
 SV_MAX_QUBITS_C64, SV_MAX_QUBITS_C128, SV_MAX_FUSED = 34, 33, 5
+SV_FUSE_TILED = -1
 
 STATUS_NAMES = {0: "SV_OK", 1: "SV_PENDING", -1: "SV_E_INVALID", -2: "SV_E_OOM", -3: "SV_E_DEVICE",
                 -4: "SV_E_NUMERIC", -5: "SV_E_NOTFOUND", -6: "SV_E_BUSY", -7: "SV_E_UNSUPPORTED"}
@@ -98,6 +99,7 @@ PROTOTYPES = {
     "sv_gate_matrix": [I32, DP, I32, DP, IP, IP],
     "sv_run": [P, ctypes.POINTER(sv_op), I32, I32],
     "sv_plan_fusion": [ctypes.POINTER(sv_op), I32, I32, I32, IP, IP],
+    "sv_plan_passes": [ctypes.POINTER(sv_op), I32, I32, I32, IP],
     "sv_norm": [P, DP],
     "sv_renormalize": [P],
     "sv_sample": [P, I64, U64, U64P],

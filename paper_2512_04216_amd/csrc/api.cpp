@@ -148,6 +148,50 @@ int ParamRing::acquire() {
 
 void ParamRing::release_after(int slot, hipStream_t s) { hipEventRecord(ev[slot], s); }
 
+int StagePool::acquire(Arena &arena, uint64_t bytes) {
+    std::lock_guard<std::mutex> g(mu);
+    for (size_t i = 0; i < bufs.size(); ++i) {
+        StageBuf &b = bufs[i];
+        if (b.bytes < bytes) continue;
+        if (b.busy && hipEventQuery(b.ev) != hipSuccess) continue;
+        b.busy = true;
+        return (int)i;
+    }
+    uint64_t sz = 64 << 10;
+    while (sz < bytes) sz <<= 1;
+    StageBuf b;
+    b.bytes = sz;
+    b.dev = (char *)arena.alloc(sz);
+    if (!b.dev) return -1;
+    if (hipHostMalloc((void **)&b.host, sz, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess) {
+        if (b.host) hipHostFree(b.host);
+        arena.free(b.dev);
+        return -1;
+    }
+    b.busy = true;
+    bufs.push_back(b);
+    return (int)bufs.size() - 1;
+}
+
+void StagePool::release_after(int i, hipStream_t s) {
+    std::lock_guard<std::mutex> g(mu);
+    hipEventRecord(bufs[i].ev, s);
+}
+
+void StagePool::destroy(Arena &arena) {
+    std::lock_guard<std::mutex> g(mu);
+    for (StageBuf &b : bufs) {
+        if (b.ev) {
+            hipEventSynchronize(b.ev);
+            hipEventDestroy(b.ev);
+        }
+        if (b.host) hipHostFree(b.host);
+        if (b.dev) arena.free(b.dev);
+    }
+    bufs.clear();
+}
+
 uint64_t state_bytes(int n, sv_dtype dt) {
     const uint64_t b = (1ull << n) * (dt == SV_C64 ? 8ull : 16ull);
     return std::max<uint64_t>(b, 16);
@@ -228,6 +272,43 @@ static sv_status validate_ops(sv_state st, const sv_op *ops, int nops) {
     return SV_OK;
 }
 
+// Tiled passes: records of every pass staged once, then one launch per pass.
+template <class After>
+sv_status run_tiled(sv_state st, const sv_op *ops, int nops, After &after) {
+    std::vector<TiledOp> tops;
+    if (!tiled_ops(ops, nops, tops)) return fail(SV_E_INVALID, "unknown gate kind");
+    if (tops.empty()) return SV_OK;
+    const int is_c64 = st->is_c64() ? 1 : 0;
+    const int mbmax = svk::tile_bits(is_c64), lbf = svk::low_bits(is_c64);
+    const auto passes = plan_passes(tops, st->n, mbmax, lbf);
+    std::vector<svk::TileGate> recs;
+    std::vector<svk::TileArgs> args(passes.size());
+    for (size_t p = 0; p < passes.size(); ++p) {
+        args[p].gate0 = (int)recs.size();
+        pass_records(tops, passes[p], st->n, mbmax, lbf, recs, args[p]);
+    }
+    sv_ctx c = st->ctx;
+    const uint64_t bytes = recs.size() * sizeof(svk::TileGate);
+    const int b = c->stage.acquire(c->arena, bytes);
+    if (b < 0) return fail(SV_E_OOM, "no memory to stage the tiled passes");
+    StageBuf &sb = c->stage.bufs[b];
+    memcpy(sb.host, recs.data(), bytes);
+    hipError_t e = hipMemcpyAsync(sb.dev, sb.host, bytes, hipMemcpyHostToDevice, st->stream);
+    sv_status r = SV_OK;
+    if (e != hipSuccess) r = hip_fail(e, "staging tiled passes");
+    const int s = is_c64 ? 8 : 16;
+    for (size_t p = 0; p < passes.size() && r == SV_OK; ++p) {
+        {
+            TraceScope ts(&c->tracer, st->stream, "tiled_pass", 2.0 * s * std::ldexp(1.0, st->n));
+            e = svk::launch_tiled(args[p], (const svk::TileGate *)sb.dev, st->psi, is_c64, st->stream);
+        }
+        if (e != hipSuccess) r = hip_fail(e, "tiled pass launch");
+        if (r == SV_OK) r = after(1);
+    }
+    c->stage.release_after(b, st->stream);
+    return r;
+}
+
 }  // namespace svh
 
 using namespace svh;
@@ -296,6 +377,7 @@ sv_status sv_ctx_destroy(sv_ctx c) {
         for (auto e : c->tracer.pool) hipEventDestroy(e);
     }
     c->ring.destroy();
+    c->stage.destroy(c->arena);
     if (c->own_stream) hipStreamDestroy(c->stream);
     if (c->own_arena) hipFree(c->arena_base);
     delete c;
@@ -479,6 +561,22 @@ sv_status sv_apply_fused(sv_state st, const double *U, int k, const int *targets
     return apply_fused(st, reinterpret_cast<const cd *>(U), k, targets);
 }
 
+sv_status sv_plan_passes(const sv_op *ops, int nops, int n, sv_dtype dt, int *npasses) {
+    if ((!ops && nops) || nops < 0 || !npasses) return fail(SV_E_INVALID, "bad argument");
+    if (n < 1 || n > (dt == SV_C64 ? SV_MAX_QUBITS_C64 : SV_MAX_QUBITS_C128)) return fail(SV_E_INVALID, "n out of range");
+    for (int i = 0; i < nops; ++i) {
+        const int nq = gate_nqubits(ops[i].kind);
+        if (nq < 0) return fail(SV_E_INVALID, "unknown gate kind");
+        for (int j = 0; j < nq; ++j)
+            if (ops[i].q[j] < 0 || ops[i].q[j] >= n) return fail(SV_E_INVALID, "qubit index out of range");
+    }
+    std::vector<TiledOp> tops;
+    if (!tiled_ops(ops, nops, tops)) return fail(SV_E_INVALID, "unknown gate kind");
+    const int is_c64 = dt == SV_C64 ? 1 : 0;
+    *npasses = tops.empty() ? 0 : (int)plan_passes(tops, n, svk::tile_bits(is_c64), svk::low_bits(is_c64)).size();
+    return SV_OK;
+}
+
 sv_status sv_plan_fusion(const sv_op *ops, int nops, int n, int fuse_k, int *nblocks, int *nsingle) {
     if ((!ops && nops) || nops < 0) return fail(SV_E_INVALID, "bad op list");
     if (fuse_k < 2 || fuse_k > SV_MAX_FUSED) return fail(SV_E_INVALID, "fuse_k out of range [2, 5]");
@@ -498,7 +596,8 @@ sv_status sv_plan_fusion(const sv_op *ops, int nops, int n, int fuse_k, int *nbl
 
 sv_status sv_run(sv_state st, const sv_op *ops, int nops, int fuse_k) {
     if (!st || (!ops && nops) || nops < 0) return fail(SV_E_INVALID, "bad argument");
-    if (fuse_k != 0 && (fuse_k < 2 || fuse_k > SV_MAX_FUSED)) return fail(SV_E_INVALID, "fuse_k must be 0 or 2..5");
+    if (fuse_k != 0 && fuse_k != SV_FUSE_TILED && (fuse_k < 2 || fuse_k > SV_MAX_FUSED))
+        return fail(SV_E_INVALID, "fuse_k must be 0, 2..5 or SV_FUSE_TILED");
     sv_status r = validate_ops(st, ops, nops);
     if (r) return r;
     const int R = st->is_c64() ? st->ctx->renorm_period : 0;
@@ -508,7 +607,10 @@ sv_status sv_run(sv_state st, const sv_op *ops, int nops, int fuse_k) {
         if (st->sweeps_since_renorm >= R) return renorm(st);
         return SV_OK;
     };
-    if (fuse_k == 0 || std::min(fuse_k, st->n) < 2) {
+    if (fuse_k == SV_FUSE_TILED) {
+        r = run_tiled(st, ops, nops, after);
+        if (r) return r;
+    } else if (fuse_k == 0 || std::min(fuse_k, st->n) < 2) {
         for (int i = 0; i < nops; ++i) {
             r = apply_op(st, ops[i]);
             if (r) return r;

@@ -296,6 +296,126 @@ std::vector<Block> plan_fusion(const sv_op *ops, int nops, int fuse_k) {
     return out;
 }
 
+// ---- tiled passes ----------------------------------------------------------------
+bool tiled_ops(const sv_op *ops, int nops, std::vector<TiledOp> &out) {
+    out.clear();
+    out.reserve(nops);
+    for (int i = 0; i < nops; ++i) {
+        const sv_op &o = ops[i];
+        cd U[16];
+        int k, nc;
+        if (!gate_matrix(o.kind, o.p, (o.flags & SV_OP_ADJOINT) != 0, U, &k, &nc)) return false;
+        TiledOp t;
+        t.d = classify(U, k, o.q + nc, o.q, nc);
+        for (int j = 0; j < k + nc; ++j) t.all |= 1ull << o.q[j];
+        if (t.d.kind == GateDesc::NOOP) continue;
+        if (t.d.kind == GateDesc::GROUP) t.mix = t.d.group.F[0] | t.d.group.F[1];
+        else if (t.d.kind != GateDesc::DIAG) return false;   // wider than a named op can be
+        out.push_back(t);
+    }
+    return true;
+}
+
+std::vector<Pass> plan_passes(const std::vector<TiledOp> &ops, int n, int mb_max, int lb_full) {
+    const int lb = std::min(lb_full, n);
+    const int hmax = std::min(mb_max, n) - lb;
+    const uint64_t low = (1ull << lb) - 1ull;
+    std::vector<Pass> out;
+    std::vector<char> done(ops.size(), 0);
+    size_t left = ops.size(), first = 0;
+    while (left > 0) {
+        while (done[first]) ++first;
+        uint64_t Q = low, blocked = 0;
+        int h = 0;
+        Pass p;
+        for (size_t i = first; i < ops.size(); ++i) {
+            if (done[i]) continue;
+            const TiledOp &t = ops[i];
+            if (t.all & blocked) {
+                blocked |= t.all;
+                continue;
+            }
+            const uint64_t need = t.mix & ~Q;
+            const int c = __builtin_popcountll(need);
+            if (h + c <= hmax) {
+                Q |= need;
+                h += c;
+                p.ops.push_back((int)i);
+                done[i] = 1;
+                --left;
+            } else {
+                blocked |= t.all;
+            }
+        }
+        // fill the tile with the lowest unused qubits: longer contiguous runs
+        for (int q = lb; q < n && h < hmax; ++q)
+            if (!((Q >> q) & 1)) {
+                Q |= 1ull << q;
+                ++h;
+            }
+        for (int q = lb; q < n; ++q)
+            if ((Q >> q) & 1) p.qh.push_back(q);
+        out.push_back(std::move(p));
+    }
+    return out;
+}
+
+void pass_records(const std::vector<TiledOp> &ops, const Pass &p, int n, int mb_max, int lb_full,
+                  std::vector<svk::TileGate> &recs, svk::TileArgs &args) {
+    const int lb = std::min(lb_full, n);
+    int local[64];
+    uint64_t Q = (1ull << lb) - 1ull;
+    for (int q = 0; q < 64; ++q) local[q] = q < lb ? q : -1;
+    for (size_t j = 0; j < p.qh.size(); ++j) {
+        local[p.qh[j]] = lb + (int)j;
+        Q |= 1ull << p.qh[j];
+    }
+    auto compress = [&](uint64_t m) {
+        uint32_t r = 0;
+        for (int q = 0; q < 64; ++q)
+            if (((m >> q) & 1) && local[q] >= 0) r |= 1u << local[q];
+        return r;
+    };
+    auto fixed = [&](svk::TileGate &g, uint64_t fm, uint64_t fv) {
+        // local positions of the fixed bits are ascending because local[] is monotone
+        for (int q = 0; q < 64; ++q)
+            if (((fm >> q) & 1) && local[q] >= 0) g.ins[g.nins++] = local[q];
+        g.lv = compress(fv & fm & Q);
+        g.gm = fm & ~Q;
+        g.gv = fv & fm & ~Q;
+    };
+    for (int oi : p.ops) {
+        const TiledOp &t = ops[oi];
+        svk::TileGate g;
+        if (t.d.kind == GateDesc::GROUP) {
+            const svk::GroupGate &gg = t.d.group;
+            g.kind = 0;
+            g.K = gg.K;
+            fixed(g, gg.fm, gg.fv);
+            g.F[0] = compress(gg.F[0]);
+            g.F[1] = compress(gg.F[1]);
+            for (int i = 0; i < 2 << (2 * gg.K); ++i) g.u[i] = gg.U[i];
+        } else {
+            const svk::DiagGate &dg = t.d.diag;
+            g.kind = 1;
+            g.K = dg.k;
+            fixed(g, dg.cmask, dg.cmask);
+            for (int i = 0; i < dg.k; ++i) {
+                g.tl[i] = local[dg.targets[i]];
+                g.tg[i] = dg.targets[i];
+            }
+            for (int i = 0; i < 2 << dg.k; ++i) g.u[i] = dg.d[i];
+        }
+        recs.push_back(g);
+    }
+    args.lb = lb;
+    args.mb = lb + (int)p.qh.size();
+    for (size_t j = 0; j < p.qh.size(); ++j) args.qh[j] = p.qh[j];
+    args.ntiles = 1ull << (n - args.mb);
+    args.ngates = (int)p.ops.size();
+    (void)mb_max;
+}
+
 // Block matrix: U = G_last ... G_first on the block's qubits, built by applying
 // each gate to the rows of a K x K matrix that starts as the identity
 // (complex128, real and imaginary parts in separate row-major arrays so the

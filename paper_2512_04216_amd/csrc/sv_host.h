@@ -93,6 +93,25 @@ struct ParamRing {
     void release_after(int slot, hipStream_t s);
 };
 
+// ---- staging buffers for the gate records of tiled runs ------------------------
+// A run's records are written to pinned host memory, copied to the device on
+// the run's stream and read by its kernels; the buffer is reused once an event
+// recorded after the run's last kernel has completed.
+struct StageBuf {
+    char *host = nullptr, *dev = nullptr;
+    uint64_t bytes = 0;
+    hipEvent_t ev = nullptr;
+    bool busy = false;
+};
+struct StagePool {
+    std::mutex mu;
+    std::vector<StageBuf> bufs;
+    // index of a free buffer of at least `bytes` (allocating one from `arena`), or -1
+    int acquire(Arena &arena, uint64_t bytes);
+    void release_after(int i, hipStream_t s);
+    void destroy(Arena &arena);
+};
+
 }  // namespace svh
 
 struct sv_ctx_s {
@@ -105,6 +124,7 @@ struct sv_ctx_s {
     int renorm_period = 0;
     svh::Tracer tracer;
     svh::ParamRing ring;
+    svh::StagePool stage;
     int nstates = 0;
     std::mutex mu;
 };
@@ -157,6 +177,27 @@ struct Block {
 std::vector<Block> plan_fusion(const sv_op *ops, int nops, int fuse_k);
 // U of a block on its qubits (bit j of the index <-> qubits[j])
 void block_matrix(const sv_op *ops, const Block &b, std::vector<cd> &U);
+
+// multi-gate tiled passes
+struct TiledOp {
+    GateDesc d;          // classification of the op (NOOP ops are dropped)
+    uint64_t mix = 0;    // qubits the op mixes amplitudes across (group flip bits)
+    uint64_t all = 0;    // every qubit the op touches
+};
+struct Pass {
+    std::vector<int> qh;     // high tile qubits, ascending
+    std::vector<int> ops;    // indices into the TiledOp list, in application order
+};
+// Classify each op for tiled passes.
+bool tiled_ops(const sv_op *ops, int nops, std::vector<TiledOp> &out);
+// Greedy pass planning: each pass takes, in circuit order, every op whose mixed
+// qubits fit the pass's tile qubits (the lb lowest, plus up to mb - lb chosen
+// while scanning) and that shares no qubit with an op left for a later pass.
+std::vector<Pass> plan_passes(const std::vector<TiledOp> &ops, int n, int mb_max, int lb_full);
+// Tile-local records of one pass, appended to `recs`; fills the pass's launch arguments
+// except gate0 (the caller's offset into its record array).
+void pass_records(const std::vector<TiledOp> &ops, const Pass &p, int n, int mb_max, int lb_full,
+                  std::vector<svk::TileGate> &recs, svk::TileArgs &args);
 
 // measurement drivers
 sv_status norm_device(sv_state st);   // leaves ||psi||^2 at norm2_dev_ptr

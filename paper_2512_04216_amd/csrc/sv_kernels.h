@@ -77,6 +77,41 @@ hipError_t launch_fused_staged(const double *U, int k, const int *targets, void 
                                int is_c64, hipStream_t s, int use_mfma, void *args_dev,
                                void *args_host);
 
+// ---- multi-gate passes over LDS tiles -----------------------------------
+// A pass loads tiles of 2^mb amplitudes into LDS: local index bits [0, lb)
+// are the state's bits [0, lb) (contiguous runs, coalesced), local bits
+// [lb, mb) are the state's bits qh[0..mb-lb) (ascending). Every gate of the
+// pass is applied to the tile in order, then the tile is written back, so a
+// pass costs one read and one write of the state whatever its gate count.
+// A gate fits a pass if the qubits it mixes (its flip bits) are tile bits;
+// controls, fixed patterns and diagonal factors may use any bit, since each
+// tile knows the global index of its amplitudes.
+inline int tile_bits(int is_c64) { return is_c64 ? 14 : 13; }   // 128 KiB of LDS per tile
+
+// One gate in tile-local form.
+struct TileGate {
+    int32_t kind = 0;       // 0: group (K flip vectors), 1: diagonal
+    int32_t K = 0;          // group: flip vectors (0..2); diagonal: targets (1..4)
+    int32_t nins = 0;       // local bits fixed by the gate, ascending: zeros inserted when
+    int32_t ins[7] = {0};   //   enumerating its base members
+    uint32_t lv = 0;        // values of those local bits in the base member
+    uint32_t F[2] = {0, 0}; // group: local flip vectors
+    int32_t tl[4] = {0};    // diagonal: local position of target i, -1 if not a tile bit
+    int32_t tg[4] = {0};    // diagonal: global position of target i
+    uint64_t gm = 0, gv = 0;// bits outside the tile that must equal gv (else the gate skips the tile)
+    double u[32] = {0};     // group: 2^K x 2^K matrix; diagonal: 2^K factors (complex128)
+};
+
+struct TileArgs {
+    uint64_t ntiles = 0;
+    int mb = 0, lb = 0;     // tile bits, low contiguous bits
+    int qh[16] = {0};       // global positions of local bits lb..mb-1
+    int gate0 = 0, ngates = 0;   // the pass's gate records in the record array
+};
+
+// gates_dev: device array of TileGate (the pass uses [gate0, gate0 + ngates)).
+hipError_t launch_tiled(const TileArgs &a, const TileGate *gates_dev, void *psi, int is_c64, hipStream_t s);
+
 // ---- measurement (FP64, compensated) -----------------------------------
 // Workspace needs (bytes) for a state of n qubits.
 uint64_t measure_workspace_bytes(int n);
