@@ -285,7 +285,8 @@ sv_status run_tiled(sv_state st, const sv_op *ops, int nops, After &after) {
     std::vector<svk::TileArgs> args(passes.size());
     for (size_t p = 0; p < passes.size(); ++p) {
         args[p].gate0 = (int)recs.size();
-        pass_records(tops, passes[p], st->n, mbmax, lbf, recs, args[p]);
+        pass_records(ops, tops, passes[p], st->n, mbmax, lbf, recs, args[p]);
+        args[p].ngates = (int)recs.size() - args[p].gate0;
     }
     sv_ctx c = st->ctx;
     const uint64_t bytes = recs.size() * sizeof(svk::TileGate);

@@ -306,6 +306,7 @@ bool tiled_ops(const sv_op *ops, int nops, std::vector<TiledOp> &out) {
         int k, nc;
         if (!gate_matrix(o.kind, o.p, (o.flags & SV_OP_ADJOINT) != 0, U, &k, &nc)) return false;
         TiledOp t;
+        t.op = i;
         t.d = classify(U, k, o.q + nc, o.q, nc);
         for (int j = 0; j < k + nc; ++j) t.all |= 1ull << o.q[j];
         if (t.d.kind == GateDesc::NOOP) continue;
@@ -360,8 +361,8 @@ std::vector<Pass> plan_passes(const std::vector<TiledOp> &ops, int n, int mb_max
     return out;
 }
 
-void pass_records(const std::vector<TiledOp> &ops, const Pass &p, int n, int mb_max, int lb_full,
-                  std::vector<svk::TileGate> &recs, svk::TileArgs &args) {
+void pass_records(const sv_op *sops, const std::vector<TiledOp> &ops, const Pass &p, int n, int mb_max,
+                  int lb_full, std::vector<svk::TileGate> &recs, svk::TileArgs &args) {
     const int lb = std::min(lb_full, n);
     int local[64];
     uint64_t Q = (1ull << lb) - 1ull;
@@ -384,11 +385,18 @@ void pass_records(const std::vector<TiledOp> &ops, const Pass &p, int n, int mb_
         g.gm = fm & ~Q;
         g.gv = fv & fm & ~Q;
     };
-    for (int oi : p.ops) {
-        const TiledOp &t = ops[oi];
+    auto targets = [&](svk::TileGate &g, int k, const int *tg) {
+        for (int i = 0; i < k; ++i) {
+            g.tl[i] = local[tg[i]];
+            g.tg[i] = tg[i];
+        }
+    };
+    // one gate description as a record
+    auto emit_desc = [&](const GateDesc &d) {
+        if (d.kind == GateDesc::NOOP) return;
         svk::TileGate g;
-        if (t.d.kind == GateDesc::GROUP) {
-            const svk::GroupGate &gg = t.d.group;
+        if (d.kind == GateDesc::GROUP) {
+            const svk::GroupGate &gg = d.group;
             g.kind = 0;
             g.K = gg.K;
             fixed(g, gg.fm, gg.fv);
@@ -396,23 +404,133 @@ void pass_records(const std::vector<TiledOp> &ops, const Pass &p, int n, int mb_
             g.F[1] = compress(gg.F[1]);
             for (int i = 0; i < 2 << (2 * gg.K); ++i) g.u[i] = gg.U[i];
         } else {
-            const svk::DiagGate &dg = t.d.diag;
+            const svk::DiagGate &dg = d.diag;
             g.kind = 1;
             g.K = dg.k;
             fixed(g, dg.cmask, dg.cmask);
-            for (int i = 0; i < dg.k; ++i) {
-                g.tl[i] = local[dg.targets[i]];
-                g.tg[i] = dg.targets[i];
-            }
+            targets(g, dg.k, dg.targets);
             for (int i = 0; i < 2 << dg.k; ++i) g.u[i] = dg.d[i];
         }
         recs.push_back(g);
+    };
+    // a run of diagonal ops as one phase run
+    auto emit_run = [&](const int *idx, int cnt) {
+        svk::TileGate h;
+        h.kind = 2;
+        h.K = cnt;
+        recs.push_back(h);
+        for (int r = 0; r < cnt; ++r) {
+            const GateDesc &d = ops[idx[r]].d;
+            svk::TileGate g;
+            g.kind = 3;
+            uint64_t fm, fv;
+            {
+                fm = fv = d.diag.cmask;
+                g.K = d.diag.k;
+                targets(g, d.diag.k, d.diag.targets);
+                // the run adds the factors' angles and takes one sincos per amplitude
+                for (int m = 0; m < 1 << d.diag.k; ++m) g.u[m] = std::atan2(d.diag.d[2 * m + 1], d.diag.d[2 * m]);
+            }
+            g.pm = compress(fm & Q);
+            g.pv = compress(fv & fm & Q);
+            g.gm = fm & ~Q;
+            g.gv = fv & fm & ~Q;
+            recs.push_back(g);
+        }
+    };
+    // Phase runs take general diagonal gates (every amplitude gets a factor, as
+    // RZ and RZZ) with unit-modulus factors; a phase on one pattern (CP, CZ, S,
+    // T) touches only its members and stays a gate of its own.
+    auto is_diag = [&](int i) {
+        const GateDesc &d = ops[i].d;
+        if (d.kind != GateDesc::DIAG || d.diag.k > 2) return false;
+        for (int m = 0; m < 1 << d.diag.k; ++m)
+            if (std::fabs(std::hypot(d.diag.d[2 * m], d.diag.d[2 * m + 1]) - 1.0) > 1e-14) return false;
+        return true;
+    };
+    // Greedy blocks of <= 2 tile qubits over a stretch of ops (the fusion rule
+    // of plan_fusion: open blocks hold disjoint qubit sets; an op joins the
+    // blocks it meets while their union has <= 2 qubits, otherwise they are
+    // emitted, oldest first, before it).
+    struct Open {
+        uint64_t q;
+        std::vector<int> ops;   // indices into `ops`
+        int order;
+    };
+    std::vector<cd> U;
+    auto emit_block = [&](Open &o) {
+        if (o.ops.size() == 1) {
+            emit_desc(ops[o.ops[0]].d);
+            return;
+        }
+        std::sort(o.ops.begin(), o.ops.end());
+        Block b;
+        for (int i : o.ops) b.ops.push_back(ops[i].op);
+        for (int q = 0; q < 64; ++q)
+            if ((o.q >> q) & 1) b.qubits.push_back(q);
+        block_matrix(sops, b, U);
+        emit_desc(classify(U.data(), (int)b.qubits.size(), b.qubits.data(), nullptr, 0));
+    };
+    auto fuse_stretch = [&](const int *idx, int cnt) {
+        std::vector<Open> open;
+        int counter = 0;
+        for (int r = 0; r < cnt; ++r) {
+            const int i = idx[r];
+            const uint64_t g = ops[i].all;
+            const bool fusable = (g & ~Q) == 0 && __builtin_popcountll(g) <= 2;
+            uint64_t uni = g;
+            std::vector<int> hit;
+            for (int b = 0; b < (int)open.size(); ++b)
+                if (open[b].q & g) {
+                    hit.push_back(b);
+                    uni |= open[b].q;
+                }
+            if (fusable && __builtin_popcountll(uni) <= 2) {
+                Open merged{uni, {}, counter++};
+                for (int b : hit) merged.ops.insert(merged.ops.end(), open[b].ops.begin(), open[b].ops.end());
+                merged.ops.push_back(i);
+                for (int h = (int)hit.size() - 1; h >= 0; --h) open.erase(open.begin() + hit[h]);
+                open.push_back(std::move(merged));
+                continue;
+            }
+            std::sort(hit.begin(), hit.end(), [&](int x, int y) { return open[x].order < open[y].order; });
+            for (int b : hit) emit_block(open[b]);
+            std::sort(hit.begin(), hit.end());
+            for (int h = (int)hit.size() - 1; h >= 0; --h) open.erase(open.begin() + hit[h]);
+            if (fusable) open.push_back(Open{g, {i}, counter++});
+            else emit_desc(ops[i].d);
+        }
+        std::sort(open.begin(), open.end(), [](const Open &x, const Open &y) { return x.order < y.order; });
+        for (auto &o : open) emit_block(o);
+    };
+    constexpr int kMinRun = 3;
+    const std::vector<int> &L = p.ops;
+    const int nl = (int)L.size();
+    auto run_len = [&](int i) {
+        int j = i;
+        while (j < nl && is_diag(L[j])) ++j;
+        return j - i;
+    };
+    for (int i = 0; i < nl;) {
+        const int rl = run_len(i);
+        if (rl >= kMinRun) {
+            emit_run(&L[i], rl);
+            i += rl;
+            continue;
+        }
+        int e = i + std::max(rl, 1);
+        while (e < nl) {
+            const int r2 = run_len(e);
+            if (r2 >= kMinRun) break;
+            e += std::max(r2, 1);
+        }
+        fuse_stretch(&L[i], e - i);
+        i = e;
     }
     args.lb = lb;
     args.mb = lb + (int)p.qh.size();
     for (size_t j = 0; j < p.qh.size(); ++j) args.qh[j] = p.qh[j];
     args.ntiles = 1ull << (n - args.mb);
-    args.ngates = (int)p.ops.size();
     (void)mb_max;
 }
 

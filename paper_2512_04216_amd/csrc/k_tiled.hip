@@ -117,6 +117,51 @@ __global__ __launch_bounds__(kTT) void k_tiled(svk::TileArgs a, const svk::TileG
                     }
                 }
             }
+        } else if (g.kind == 2) {
+            // Phase run: angle sums, one sincos per amplitude. Terms entirely
+            // outside the tile give one angle for the tile, terms on thread-index
+            // bits one per thread, the others one per amplitude.
+            constexpr int APT = (1 << MB) / kTT;   // amplitudes per thread: j = tid + q * kTT
+            const uint32_t size = 1u << mb;
+            double at = 0.0, aq[APT];
+#pragma unroll
+            for (int q = 0; q < APT; ++q) aq[q] = 0.0;
+            const int nt = g.K;
+            for (int t = 0; t < nt; ++t) {
+                const svk::TileGate &h = gates[a.gate0 + gi + 1 + t];
+                if ((base & h.gm) != h.gv) continue;   // uniform
+                uint32_t mfix = 0, lmask = h.pm;
+                int t0 = -1, t1 = -1;
+                for (int i = 0; i < h.K; ++i) {
+                    if (h.tl[i] < 0) mfix |= (uint32_t)((base >> h.tg[i]) & 1u) << i;
+                    else lmask |= 1u << h.tl[i];
+                }
+                if (h.K > 0) t0 = h.tl[0];
+                if (h.K > 1) t1 = h.tl[1];
+                const double a0 = h.u[0], a1 = h.u[1], a2 = h.u[2], a3 = h.u[3];
+                auto ang = [&](uint32_t j) {
+                    uint32_t m = mfix;
+                    if (t0 >= 0) m |= (j >> t0) & 1u;
+                    if (t1 >= 0) m |= ((j >> t1) & 1u) << 1;
+                    const double lo = (m & 1u) ? a1 : a0, hi = (m & 1u) ? a3 : a2;
+                    return ((j & h.pm) == h.pv) ? ((m & 2u) ? hi : lo) : 0.0;
+                };
+                if (lmask < (uint32_t)kTT) {
+                    at += ang((uint32_t)tid);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < APT; ++q) aq[q] += ang((uint32_t)tid + q * kTT);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < APT; ++q) {
+                const uint32_t j = tid + q * kTT;
+                if (j >= size) continue;
+                double sn, cs;
+                sincos(at + aq[q], &sn, &cs);
+                lds[j] = cmul(Cx<T>{(T)cs, (T)sn}, lds[j]);
+            }
+            gi += nt;
         } else {
             // diagonal: factor index from the target bits, the ones outside the tile fixed
             uint32_t mfix = 0;

@@ -180,6 +180,7 @@ void block_matrix(const sv_op *ops, const Block &b, std::vector<cd> &U);
 
 // multi-gate tiled passes
 struct TiledOp {
+    int op = 0;          // index in the sv_op list
     GateDesc d;          // classification of the op (NOOP ops are dropped)
     uint64_t mix = 0;    // qubits the op mixes amplitudes across (group flip bits)
     uint64_t all = 0;    // every qubit the op touches
@@ -195,9 +196,12 @@ bool tiled_ops(const sv_op *ops, int nops, std::vector<TiledOp> &out);
 // while scanning) and that shares no qubit with an op left for a later pass.
 std::vector<Pass> plan_passes(const std::vector<TiledOp> &ops, int n, int mb_max, int lb_full);
 // Tile-local records of one pass, appended to `recs`; fills the pass's launch arguments
-// except gate0 (the caller's offset into its record array).
-void pass_records(const std::vector<TiledOp> &ops, const Pass &p, int n, int mb_max, int lb_full,
-                  std::vector<svk::TileGate> &recs, svk::TileArgs &args);
+// except gate0 (the caller's offset into its record array). Inside the pass,
+// runs of 3 or more consecutive diagonal ops become one phase run, and the
+// other ops whose qubits are tile qubits are merged greedily into blocks of at
+// most 2 qubits (block matrices formed in complex128 as for fused blocks).
+void pass_records(const sv_op *sops, const std::vector<TiledOp> &ops, const Pass &p, int n, int mb_max,
+                  int lb_full, std::vector<svk::TileGate> &recs, svk::TileArgs &args);
 
 // measurement drivers
 sv_status norm_device(sv_state st);   // leaves ||psi||^2 at norm2_dev_ptr

@@ -88,18 +88,24 @@ hipError_t launch_fused_staged(const double *U, int k, const int *targets, void 
 // tile knows the global index of its amplitudes.
 inline int tile_bits(int is_c64) { return is_c64 ? 14 : 13; }   // 128 KiB of LDS per tile
 
-// One gate in tile-local form.
+// One gate in tile-local form. kind 2 heads a phase run: the K records after it
+// (kind 3) are diagonal gates with unit-modulus factors whose angles add into
+// one phase per amplitude, applied in a single sweep of the tile; a kind-3
+// record applies where (j & pm) == pv and (global index & gm) == gv, with angle
+// u[m], m = its target bits.
 struct TileGate {
-    int32_t kind = 0;       // 0: group (K flip vectors), 1: diagonal
-    int32_t K = 0;          // group: flip vectors (0..2); diagonal: targets (1..4)
+    int32_t kind = 0;       // 0: group (K flip vectors), 1: diagonal, 2: phase run, 3: run term
+    int32_t K = 0;          // group: flip vectors (0..2); diagonal, run term: targets (0..2); run: terms
     int32_t nins = 0;       // local bits fixed by the gate, ascending: zeros inserted when
     int32_t ins[7] = {0};   //   enumerating its base members
     uint32_t lv = 0;        // values of those local bits in the base member
     uint32_t F[2] = {0, 0}; // group: local flip vectors
+    uint32_t pm = 0, pv = 0;// run term: local pattern mask and value
     int32_t tl[4] = {0};    // diagonal: local position of target i, -1 if not a tile bit
     int32_t tg[4] = {0};    // diagonal: global position of target i
     uint64_t gm = 0, gv = 0;// bits outside the tile that must equal gv (else the gate skips the tile)
-    double u[32] = {0};     // group: 2^K x 2^K matrix; diagonal: 2^K factors (complex128)
+    double u[32] = {0};     // group: 2^K x 2^K matrix; diagonal: 2^K factors (complex128);
+                            // run term: 2^K angles
 };
 
 struct TileArgs {

@@ -106,3 +106,44 @@ def test_tiled_runs_back_to_back(ctx, S, O):
         st.run(a, fuse_k=TILED)
         got = st.copy_out()
     assert np.max(np.abs(got - want)) <= C128_TOL
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_diagonal_runs_tiled(ctx, S, O, dtype):
+    # long runs of diagonal gates (one phase-run record per run) between
+    # layers of Hadamards, with targets and controls inside and outside tiles
+    n = 18
+    diag = ["z", "s", "sdg", "t", "tdg", "rz", "p", "cz", "cp", "rzz"]
+    ops = []
+    for layer in range(4):
+        ops += [("h", (q,), ()) for q in range(n)]
+        ops += W.random_circuit(n, 60, seed=50 + layer, names=diag)
+    ops += [("ccx", (17, 16, 2), ()), ("cx", (15, 1), ())] + W.random_circuit(n, 10, seed=99, names=diag)
+    psi0 = _start(n, 77, dtype)
+    want = O.run(ops, n, psi=psi0.copy())
+    with S.State(ctx, n, dtype) as st:
+        st.copy_in(psi0)
+        st.run(ops, fuse_k=TILED)
+        got = st.copy_out()
+    if dtype == "c128":
+        assert np.max(np.abs(got - want)) <= C128_TOL
+    else:
+        assert infidelity(got, want) <= 1e-5
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_qaoa_tiled(ctx, S, O, dtype):
+    n = 18
+    ops, _edges, terms = W.qaoa_maxcut(n, 3, seed=31)
+    want = O.run(ops, n)
+    with S.State(ctx, n, dtype) as st:
+        st.run(ops, fuse_k=TILED)
+        got = st.copy_out()
+        vals, _ = st.expect(terms)
+    want_e = np.array([O.expect(want, x, z).real for x, z, _ in terms])
+    if dtype == "c128":
+        assert np.max(np.abs(got - want)) <= C128_TOL
+        assert np.max(np.abs(vals - want_e)) <= 1e-12
+    else:
+        assert infidelity(got, want) <= 1e-5
+        assert np.max(np.abs(vals - want_e)) <= 2 * math.sqrt(1e-5)
