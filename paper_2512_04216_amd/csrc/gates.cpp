@@ -324,11 +324,12 @@ std::vector<Pass> plan_passes(const std::vector<TiledOp> &ops, int n, int mb_max
     std::vector<Pass> out;
     std::vector<char> done(ops.size(), 0);
     size_t left = ops.size(), first = 0;
-    while (left > 0) {
-        while (done[first]) ++first;
-        uint64_t Q = low, blocked = 0;
-        int h = 0;
-        Pass p;
+    // One scan over the unplaced ops: take, in order, every op whose mixed
+    // qubits are (or, with `grow`, can still be added to) the tile qubits Q and
+    // that shares no qubit with an op left for later.
+    auto scan = [&](uint64_t Q, bool grow, std::vector<int> *take, uint64_t *Qout) {
+        uint64_t blocked = 0;
+        int h = __builtin_popcountll(Q & ~low), cnt = 0;
         for (size_t i = first; i < ops.size(); ++i) {
             if (done[i]) continue;
             const TiledOp &t = ops[i];
@@ -338,17 +339,60 @@ std::vector<Pass> plan_passes(const std::vector<TiledOp> &ops, int n, int mb_max
             }
             const uint64_t need = t.mix & ~Q;
             const int c = __builtin_popcountll(need);
-            if (h + c <= hmax) {
+            if (c == 0 || (grow && h + c <= hmax)) {
                 Q |= need;
                 h += c;
-                p.ops.push_back((int)i);
-                done[i] = 1;
-                --left;
+                ++cnt;
+                if (take) take->push_back((int)i);
             } else {
                 blocked |= t.all;
             }
         }
+        if (Qout) *Qout = Q;
+        return cnt;
+    };
+    while (left > 0) {
+        while (done[first]) ++first;
+        // candidate tile sets: the greedy growing one, every window of hmax
+        // consecutive qubits above the low ones, and the qubits the next
+        // unplaced ops use most; the one that takes the most ops wins
+        uint64_t bestQ = low;
+        bool best_grow = true;
+        int best = scan(low, true, nullptr, &bestQ);
+        auto consider = [&](uint64_t Q) {
+            const int c = scan(Q, false, nullptr, nullptr);
+            if (c > best) {
+                best = c;
+                bestQ = Q;
+                best_grow = false;
+            }
+        };
+        if (hmax > 0) {
+            for (int s0 = lb; s0 + hmax <= n; ++s0) consider(low | (((1ull << hmax) - 1ull) << s0));
+            int score[64] = {0};
+            int seen = 0;
+            for (size_t i = first; i < ops.size() && seen < 256; ++i) {
+                if (done[i]) continue;
+                ++seen;
+                for (int q = lb; q < n; ++q) score[q] += (int)(((ops[i].mix >> q) & 1) * 2 + ((ops[i].all >> q) & 1));
+            }
+            uint64_t Q = low;
+            for (int k = 0; k < hmax; ++k) {
+                int bq = -1;
+                for (int q = lb; q < n; ++q)
+                    if (!((Q >> q) & 1) && (bq < 0 || score[q] > score[bq])) bq = q;
+                if (bq < 0) break;
+                Q |= 1ull << bq;
+            }
+            consider(Q);
+        }
+        Pass p;
+        uint64_t Q = bestQ;
+        scan(bestQ, best_grow, &p.ops, &Q);
+        for (int i : p.ops) done[i] = 1;
+        left -= p.ops.size();
         // fill the tile with the lowest unused qubits: longer contiguous runs
+        int h = __builtin_popcountll(Q & ~low);
         for (int q = lb; q < n && h < hmax; ++q)
             if (!((Q >> q) & 1)) {
                 Q |= 1ull << q;

@@ -117,7 +117,7 @@ def test_tiled_pass_counts():
     import paper_2512_04216_amd as S
 
     assert S.sv_plan_passes(W.qft(28), 28, "c128") == 7
-    assert S.sv_plan_passes(W.brickwork(28, 20, seed=20251205), 28, "c128") == 30
+    assert S.sv_plan_passes(W.brickwork(28, 20, seed=20251205), 28, "c128") == 16
     assert S.sv_plan_passes(W.brickwork(13, 20, seed=1), 13, "c128") == 1
     assert S.sv_plan_passes(W.brickwork(14, 20, seed=1), 14, "c64") == 1
     assert S.sv_plan_passes(W.brickwork(14, 20, seed=1), 14, "c128") > 1
