@@ -306,9 +306,9 @@ def bench_serving(S, count=10000, baseline_count=300, loads=(0.5, 0.8, 0.95)):
     import numpy as np  # noqa: F811
 
     best = None
-    for fk in (5, 0):
+    for fk in (-1, 5, 0):
         r = run(fk)
-        out["saturated_fuse%d" % fk] = r
+        out["saturated_%s" % ("tiled" if fk < 0 else "fuse%d" % fk)] = r
         print("bench serving: saturated fuse_k=%d %s" % (fk, r), file=sys.stderr, flush=True)
         if best is None or r["circuits_per_s"] > best[1]["circuits_per_s"]:
             best = (fk, r)

@@ -77,7 +77,8 @@ struct Req {
     std::vector<uint32_t> bref;              // index into smallU (x16) or fl
     std::vector<cd> smallU;
     std::vector<svk::FusedLaunch> fl;
-    char *ahost = nullptr, *adev = nullptr;  // argument blocks (pinned / device)
+    std::vector<svk::TileArgs> targs;        // tiled passes (fuse_k = SV_FUSE_TILED)
+    char *ahost = nullptr, *adev = nullptr;  // argument blocks or pass records (pinned / device)
     uint64_t astride = 0;
     size_t next = 0, total = 0;
     bool measuring = false;
@@ -196,7 +197,43 @@ bool try_admit_large(sv_server s, Req *r) {
     }
     r->next = 0;
     r->measuring = false;
-    r->prepared = r->fuse_k < 2;
+    r->prepared = r->fuse_k == 0;
+    return true;
+}
+
+// Tiled passes of a request: plan, records staged in one transfer.
+bool prepare_passes(sv_server s, Req *r) {
+    std::vector<TiledOp> tops;
+    tiled_ops(r->ops.data(), (int)r->ops.size(), tops);   // ops were validated at submission
+    const int is_c64 = r->st->is_c64() ? 1 : 0;
+    const int mbmax = svk::tile_bits(is_c64), lbf = svk::low_bits(is_c64);
+    const auto passes = tops.empty() ? std::vector<Pass>() : plan_passes(tops, r->n, mbmax, lbf);
+    std::vector<svk::TileGate> recs;
+    r->targs.assign(passes.size(), svk::TileArgs{});
+    for (size_t p = 0; p < passes.size(); ++p) {
+        r->targs[p].gate0 = (int)recs.size();
+        pass_records(r->ops.data(), tops, passes[p], r->n, mbmax, lbf, recs, r->targs[p]);
+        r->targs[p].ngates = (int)recs.size() - r->targs[p].gate0;
+    }
+    const uint64_t bytes = recs.size() * sizeof(svk::TileGate);
+    if (bytes > 0) {
+        r->ahost = (char *)s->pinned.alloc(bytes);
+        r->adev = r->ahost ? (char *)s->ctx->arena.alloc(bytes) : nullptr;
+        if (!r->ahost || !r->adev) {
+            if (r->ahost) s->pinned.free(r->ahost);
+            r->ahost = nullptr;
+            return false;
+        }
+        memcpy(r->ahost, recs.data(), bytes);
+        if (hipMemcpyAsync(r->adev, r->ahost, bytes, hipMemcpyHostToDevice, r->st->stream) != hipSuccess) {
+            s->ctx->arena.free(r->adev);
+            s->pinned.free(r->ahost);
+            r->adev = r->ahost = nullptr;
+            return false;
+        }
+    }
+    r->total = passes.size();
+    r->prepared = true;
     return true;
 }
 
@@ -497,11 +534,16 @@ bool advance_large(sv_server s) {
     for (Req *r : s->large) {
         if (r->measuring) continue;
         const int R = r->st->is_c64() ? s->ctx->renorm_period : 0;
-        if (!r->prepared && !prepare_blocks(s, r)) continue;
+        if (!r->prepared && !(r->fuse_k == SV_FUSE_TILED ? prepare_passes(s, r) : prepare_blocks(s, r))) continue;
         int budget = kChunk;
         sv_status q = SV_OK;
         while (budget > 0 && r->next < r->total && q == SV_OK) {
-            if (r->fuse_k >= 2) {
+            if (r->fuse_k == SV_FUSE_TILED) {
+                TraceScope ts(&s->ctx->tracer, r->st->stream, "tiled_pass", 2.0 * (double)r->st->bytes);
+                const hipError_t e = svk::launch_tiled(r->targs[r->next], (const svk::TileGate *)r->adev, r->st->psi,
+                                                       r->st->is_c64() ? 1 : 0, r->st->stream);
+                if (e != hipSuccess) q = hip_fail(e, "tiled pass launch");
+            } else if (r->fuse_k >= 2) {
                 const size_t j = r->next;
                 const Block &b = r->blocks[j];
                 if (r->bkind[j] == 0) {
@@ -611,7 +653,8 @@ sv_status validate(sv_server s, const sv_circuit *c) {
     if (c->nops < 0 || (c->nops > 0 && !c->ops)) return fail(SV_E_INVALID, "bad op list");
     if (c->nterms < 0 || (c->nterms > 0 && !c->terms)) return fail(SV_E_INVALID, "bad term list");
     if (c->shots < 0 || c->shots > kMaxShots) return fail(SV_E_INVALID, "shots out of range [0, 2^24]");
-    if (c->fuse_k != 0 && (c->fuse_k < 2 || c->fuse_k > SV_MAX_FUSED)) return fail(SV_E_INVALID, "fuse_k must be 0 or 2..5");
+    if (c->fuse_k != 0 && c->fuse_k != SV_FUSE_TILED && (c->fuse_k < 2 || c->fuse_k > SV_MAX_FUSED))
+        return fail(SV_E_INVALID, "fuse_k must be 0, 2..5 or SV_FUSE_TILED");
     for (int i = 0; i < c->nops; ++i) {
         const sv_op &o = c->ops[i];
         const int nq = gate_nqubits(o.kind);

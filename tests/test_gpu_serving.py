@@ -50,7 +50,7 @@ def _check_vs_oracle(O, r, res):
 
 
 def test_serving_matches_oracle(ctx, S, O):
-    reqs = _requests(1, 80, 3, 16, fuse=(0, 0, 5))
+    reqs = _requests(1, 90, 3, 16, fuse=(0, 5, -1))
     with S.Server(ctx) as srv:
         ids = [_submit(srv, r) for r in reqs]
         results = [srv.wait(i, 60000) for i in ids]
@@ -64,13 +64,13 @@ def test_serving_matches_oracle(ctx, S, O):
 
 def test_serving_stream_spot_checks(ctx, S, O):
     # 240 requests of the serving recipe (complex64, fused blocks of <= 5
-    # qubits, 1000 shots), qubit counts 8..18 so the oracle finishes quickly:
-    # packed small circuits and resident states in one mix.
+    # qubits or tiled passes, 1000 shots), qubit counts 8..18 so the oracle
+    # finishes quickly: packed small circuits and resident states in one mix.
     reqs = W.serving_stream(240, seed=20251211, n_lo=8, n_hi=18)
     for i, r in enumerate(reqs):
         n = r["n"]
         r["terms"] = [(0, 0b11 << (i % (n - 1)), 1.0), (1 << (i % n), 0, 0.5)]
-        r["dtype"], r["fuse_k"] = "c64", 5
+        r["dtype"], r["fuse_k"] = "c64", (5, -1)[i % 2]
     with S.Server(ctx) as srv:
         ids = [_submit(srv, r) for r in reqs]
         results = [srv.wait(i, 120000) for i in ids]
@@ -82,7 +82,7 @@ def test_serving_stream_spot_checks(ctx, S, O):
 
 
 def test_alone_equals_mix_bitwise(ctx, S):
-    reqs = _requests(2, 48, 4, 20, fuse=(0, 5))
+    reqs = _requests(2, 48, 4, 20, fuse=(0, 5, -1))
     with S.Server(ctx) as srv:
         alone = []
         for r in reqs:
