@@ -96,7 +96,7 @@ def cpu_baseline(budget_s=15.0):
                       "(%.1f s)" % (done, dt)}
 
 
-def run_28q(S, ctx, dtype, steps, warmup, shots=4096, trace=True):
+def run_28q(S, ctx, dtype, steps, warmup, shots=4096, trace=True, fuse_k=0):
     import torch
 
     n, brick, x, qft = workload_28q(dtype)
@@ -106,10 +106,10 @@ def run_28q(S, ctx, dtype, steps, warmup, shots=4096, trace=True):
 
     def step(i):
         st.reset(0)
-        st.run(brick)
+        st.run(brick, fuse_k=fuse_k)
         st.sample(shots, SEED + 2 * i)
         st.reset(x)
-        st.run(qft)
+        st.run(qft, fuse_k=fuse_k)
         st.sample(shots, SEED + 2 * i + 1)
 
     for i in range(warmup):
@@ -202,7 +202,8 @@ def bench_fused(S, steps=1):
         res = {"gates": len(ops)}
         nb, ns = S.sv_plan_fusion(ops, n, 5)
         res["fused_blocks"] = nb
-        for fk in (5, 0):
+        res["tiled_passes"] = S.sv_plan_passes(ops, n, dt)
+        for fk in (5, -1, 0):
             st.reset(0)
             torch.cuda.synchronize()
             ctx.trace_read()
@@ -213,9 +214,14 @@ def bench_fused(S, steps=1):
             dt_s = time.perf_counter() - t0
             ctx.trace(False)
             tr = ctx.trace_read()
-            key = "fused" if fk else "unfused"
+            key = "fused" if fk > 0 else "tiled" if fk < 0 else "unfused"
             res[key] = {"seconds": round(dt_s, 3), "gates_per_s": round(len(ops) / dt_s, 2)}
-            if fk and "fused_mfma" in tr:
+            if fk < 0 and "tiled_pass" in tr:
+                rec = tr["tiled_pass"]
+                avg = rec["seconds"] / rec["launches"]
+                res[key]["pass_kernel"] = {"launches": rec["launches"], "avg_ms": round(avg * 1e3, 3),
+                                           "GBps": round(rec["bytes"] / rec["launches"] / avg / 1e9, 1)}
+            if fk > 0 and "fused_mfma" in tr:
                 rec = tr["fused_mfma"]
                 avg = rec["seconds"] / rec["launches"]
                 amps = float(1 << n)
@@ -244,6 +250,7 @@ def bench_qaoa(S):
     arr = S.ops_to_numpy(ops)
     ctx = S.Context(arena_bytes=40 << 30)
     out = {"gates": len(ops), "edges": len(edges)}
+    out["tiled_passes"] = S.sv_plan_passes(ops, n, "c64")
     for dt in ("c128", "c64"):
         st = S.State(ctx, n, dt)
         torch.cuda.synchronize()
@@ -256,6 +263,15 @@ def bench_qaoa(S):
         t_exp = time.perf_counter() - t0
         out[dt] = {"run_s": round(t_run, 3), "gates_per_s": round(len(ops) / t_run, 1), "expect_s": round(t_exp, 4),
                    "energy": energy, "norm2": st.norm2()}
+        # the same circuit in tiled passes (phase runs fold each RZZ layer)
+        st.reset(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st.run(arr, fuse_k=S.SV_FUSE_TILED)
+        torch.cuda.synchronize()
+        t_til = time.perf_counter() - t0
+        _, e_til = st.expect(terms)
+        out[dt]["tiled"] = {"run_s": round(t_til, 3), "gates_per_s": round(len(ops) / t_til, 1), "energy": e_til}
         st.close()
     out["energy_abs_diff_c64_vs_c128"] = abs(out["c64"]["energy"] - out["c128"]["energy"])
     ctx.close()
@@ -382,6 +398,12 @@ def main():
         side = {"gates_per_s": r64["gates"] / r64["seconds"], "ms_per_step": 1e3 * r64["seconds"] / args.steps,
                 "hbm_GBps": r64["algo_bytes"] / r64["seconds"] / 1e9}
         print("bench: c64 done in %.3f s" % r64["seconds"], file=sys.stderr, flush=True)
+    # the same step in multi-gate tiled passes (not the headline: that one is per gate)
+    rt = run_28q(S, ctx, args.dtype, args.steps, args.warmup, trace=False, fuse_k=S.SV_FUSE_TILED)
+    n28, brick28, _x, qft28 = workload_28q(args.dtype)
+    tiled = {"gates_per_s": round(rt["gates"] / rt["seconds"], 1), "ms_per_step": round(1e3 * rt["seconds"] / args.steps, 3),
+             "passes_per_step": S.sv_plan_passes(brick28, n28, args.dtype) + S.sv_plan_passes(qft28, n28, args.dtype)}
+    print("bench: tiled passes done in %.3f s" % rt["seconds"], file=sys.stderr, flush=True)
     ctx.close()
 
     roof = None
@@ -417,6 +439,7 @@ def main():
     }
     if side:
         out["c64"] = {k: round(v, 2) for k, v in side.items()}
+    out["tiled"] = tiled
     print(json.dumps(out))
 
 

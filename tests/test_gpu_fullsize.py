@@ -2,7 +2,8 @@
 hold at any size and outputs computable one by one: 28-qubit brickwork mirror
 and norm, 28-qubit QFT against its closed form on sampled outputs, 30-qubit
 QAOA p=1 against the closed form, and the 33-qubit complex128 / 34-qubit
-complex64 fused path by cross-mirror (fused forward, per-gate inverse)."""
+complex64 fused and tiled paths by cross-mirror (fused blocks or tiled passes
+forward, per-gate inverse). Per-gate, fused and tiled runs are all checked."""
 import math
 
 import numpy as np
@@ -16,7 +17,7 @@ pytestmark = pytest.mark.gpu
 SEED = 20251205
 
 
-@pytest.mark.parametrize("dtype,fuse_k", [("c128", 0), ("c64", 0), ("c128", 5)])
+@pytest.mark.parametrize("dtype,fuse_k", [("c128", 0), ("c64", 0), ("c128", 5), ("c128", -1), ("c64", -1)])
 def test_brickwork_28q_mirror_and_norm(ctx, S, dtype, fuse_k):
     n = 28
     ops = W.brickwork(n, 20, seed=SEED)
@@ -30,8 +31,9 @@ def test_brickwork_28q_mirror_and_norm(ctx, S, dtype, fuse_k):
     assert 1.0 - abs(a0) ** 2 <= tol
 
 
+@pytest.mark.parametrize("fuse_k", [0, -1])
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-def test_qft_28q_closed_form_on_sampled_outputs(ctx, S, dtype):
+def test_qft_28q_closed_form_on_sampled_outputs(ctx, S, dtype, fuse_k):
     n = 28
     x = W.random_basis_state(n, SEED)
     rng = np.random.default_rng(1)
@@ -39,7 +41,7 @@ def test_qft_28q_closed_form_on_sampled_outputs(ctx, S, dtype):
                         np.array([0, 1, (1 << n) - 1], dtype=np.uint64)])
     with S.State(ctx, n, dtype) as st:
         st.reset(x)
-        st.run(W.qft(n))
+        st.run(W.qft(n), fuse_k=fuse_k)
         got = st.amplitudes(y)
         shots = st.sample(4096, SEED + 1)
     ph = ((np.uint64(x) * y) & np.uint64((1 << n) - 1)).astype(np.float64) / float(1 << n)
@@ -56,14 +58,15 @@ def test_qft_28q_closed_form_on_sampled_outputs(ctx, S, dtype):
     assert chi2 < 60.0          # 15 dof; P(chi2 > 60) < 1e-6
 
 
+@pytest.mark.parametrize("fuse_k", [0, -1])
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-def test_qaoa_30q_p1_closed_form(ctx, S, dtype):
+def test_qaoa_30q_p1_closed_form(ctx, S, dtype, fuse_k):
     n = 30
     ops, edges, terms = W.qaoa_maxcut(n, 1, seed=SEED + 4)
     gamma, beta = ops[n][2][0], ops[-1][2][0]
     want = qaoa_p1_edge_zz(gamma, beta, edges, n)
     with S.State(ctx, n, dtype) as st:
-        st.run(ops)
+        st.run(ops, fuse_k=fuse_k)
         vals, energy = st.expect(terms)
     if dtype == "c128":
         assert np.max(np.abs(vals - want)) <= 1e-12
@@ -82,11 +85,13 @@ def big_ctx(S):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("fuse_k", [5, -1])
 @pytest.mark.parametrize("n,dtype", [(33, "c128"), (34, "c64")])
-def test_fused_cross_mirror_full_size(big_ctx, S, n, dtype):
+def test_fused_cross_mirror_full_size(big_ctx, S, n, dtype, fuse_k):
+    # fused blocks or tiled passes forward, one kernel per gate backward
     ops = W.brickwork(n, 10, seed=SEED + 2)
     with S.State(big_ctx, n, dtype) as st:
-        st.run(S.ops_to_numpy(ops), fuse_k=5)
+        st.run(S.ops_to_numpy(ops), fuse_k=fuse_k)
         st.run(S.ops_to_numpy(S.inverse_ops(ops)), fuse_k=0)
         a0 = st.amplitudes([0])[0]
     tol = 1e-12 if dtype == "c128" else 1e-5
