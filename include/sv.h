@@ -139,6 +139,14 @@ typedef enum {
 
 #define SV_OP_ADJOINT 1   /* sv_op.flags: apply the conjugate transpose */
 
+/* Non-unitary op kinds, accepted by sv_run_shots only (sv_run and sv_submit
+ * reject them as unknown kinds):
+ *   SV_OP_MEASURE  measure qubit q[0] in the computational basis and store the
+ *                  outcome in classical bit q[1] (0..63) of the shot;
+ *   SV_OP_RESET    measure qubit q[0] and return it to |0> (outcome not kept). */
+#define SV_OP_MEASURE 64
+#define SV_OP_RESET 65
+
 typedef struct {
     int32_t kind;     /* sv_gate_kind */
     int32_t flags;    /* SV_OP_ADJOINT or 0 */
@@ -179,6 +187,27 @@ sv_status sv_plan_fusion(const sv_op *ops, int nops, int n, int fuse_k, int *nbl
 /* Tiled-pass plan of a gate list on n qubits of type dt without running it:
  * the number of passes (each one read and write of the state). */
 sv_status sv_plan_passes(const sv_op *ops, int nops, int n, sv_dtype dt, int *npasses);
+
+/* Run a circuit with mid-circuit measurements and resets once per shot
+ * (Sec. III-B: execution runs once up to the first measurement or reset, then
+ * the state is cloned and the shots continue separately). Starting from the
+ * state's current contents, every shot follows its own trajectory: at the k-th
+ * SV_OP_MEASURE / SV_OP_RESET (k = 0..K-1 in list order) shot s draws
+ * u = U01(seed, s*(K+1) + k) (the generator of sv_sample), computes the FP64
+ * probabilities p0, p1 of the qubit being 0 / 1 and takes outcome 1 exactly
+ * when u*(p0+p1) >= p0; the state is projected on the outcome and rescaled by
+ * 1/sqrt(p_outcome) (a reset then moves the qubit back to |0>). Shots that
+ * agree on every outcome so far share one state: a state is cloned only where
+ * their outcomes differ, and branches are finished depth-first, so at most one
+ * extra state per measurement depth is held in the arena (SV_E_OOM if a clone
+ * does not fit). The unitary ops between measurements run as sv_run with
+ * fuse_k. Outputs (caller-owned, `shots` entries each): clbits_out[s] holds the
+ * shot's classical bits (bit c = outcome of the last SV_OP_MEASURE into c, 0 if
+ * none); samples_out (nullable) the shot's terminal measurement of all qubits,
+ * the inverse-CDF draw of sv_sample with counter s*(K+1) + K. st afterwards
+ * holds the final state of one of the branches. Synchronous. */
+sv_status sv_run_shots(sv_state st, const sv_op *ops, int nops, int fuse_k, int64_t shots, uint64_t seed,
+                       uint64_t *clbits_out, uint64_t *samples_out);
 
 /* --------------------------------------------------------- measurement */
 

@@ -242,6 +242,64 @@ void or_sample(const cplx *psi, int n, int64_t shots, uint64_t seed,
     }
 }
 
+/* The same inverse-CDF draw for `count` shots whose generator counters are
+ * given: shot i uses u = U01(seed, counters[i]). */
+void or_sample_at(const cplx *psi, int n, int64_t count, uint64_t seed,
+                  const uint64_t *counters, uint64_t *out, double *F)
+{
+    const uint64_t N = 1ull << n;
+    or_cdf(psi, n, F);
+    double total = F[N - 1];
+    uint64_t last_nonzero = 0;
+    for (uint64_t i = 0; i < N; i++)
+        if (creal(psi[i]) != 0 || cimag(psi[i]) != 0) last_nonzero = i;
+    for (int64_t s = 0; s < count; s++) {
+        double r = or_u01(seed, counters[s]) * total;
+        uint64_t lo = 0, hi = N;
+        while (lo < hi) {
+            uint64_t mid = lo + (hi - lo) / 2;
+            if (F[mid] > r) hi = mid;
+            else lo = mid + 1;
+        }
+        out[s] = (lo < N) ? lo : last_nonzero;
+    }
+}
+
+/* Probabilities of qubit q being 0 and 1: Neumaier sums of |psi_i|^2 over the
+ * indices with bit q clear / set, in index order (Born rule for a measurement
+ * of one qubit in the computational basis). */
+void or_qubit_probs(const cplx *psi, int n, int q, double *p0, double *p1)
+{
+    const uint64_t N = 1ull << n;
+    neum a0 = {0, 0}, a1 = {0, 0};
+    for (uint64_t i = 0; i < N; i++) {
+        double re = creal(psi[i]), im = cimag(psi[i]);
+        neum_add(((i >> q) & 1) ? &a1 : &a0, re * re + im * im);
+    }
+    *p0 = neum_value(&a0);
+    *p1 = neum_value(&a1);
+}
+
+/* State after measuring qubit q with outcome m of probability pm: amplitudes
+ * whose bit q differs from m become 0, the others are divided by sqrt(pm). With
+ * reset set and m = 1 the surviving amplitudes then move from bit q = 1 to
+ * bit q = 0 (the qubit is returned to |0>). */
+void or_collapse(cplx *psi, int n, int q, int m, double pm, int reset)
+{
+    const uint64_t N = 1ull << n, bit = 1ull << q;
+    const double c = 1.0 / sqrt(pm);
+    for (uint64_t i = 0; i < N; i++) {
+        if ((int)((i >> q) & 1) != m) psi[i] = 0;
+        else psi[i] *= c;
+    }
+    if (reset && m == 1)
+        for (uint64_t i = 0; i < N; i++)
+            if (i & bit) {
+                psi[i ^ bit] = psi[i];
+                psi[i] = 0;
+            }
+}
+
 /* Expectation value of the Pauli string P = i^{nY} X^x Z^z, where x and z are
  * qubit bitmasks (a Y on qubit q sets bit q in both; nY = popcount(x & z)):
  * P|b> = i^{nY} (-1)^{popcount(b & z)} |b xor x>, so

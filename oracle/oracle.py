@@ -61,6 +61,15 @@ def lib():
         L.or_expect.argtypes = [_c_cplx_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.or_expect.restype = None
+        L.or_sample_at.argtypes = [_c_cplx_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.or_sample_at.restype = None
+        L.or_qubit_probs.argtypes = [_c_cplx_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]
+        L.or_qubit_probs.restype = None
+        L.or_collapse.argtypes = [_c_cplx_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                  ctypes.c_int]
+        L.or_collapse.restype = None
         _lib = L
     return _lib
 
@@ -162,6 +171,63 @@ def sample(psi: np.ndarray, shots: int, seed: int) -> np.ndarray:
     F = np.empty(psi.size, dtype=np.float64)
     lib().or_sample(_ptr(psi), n, int(shots), seed & (2**64 - 1), _ptr(out), _ptr(F))
     return out
+
+
+def sample_at(psi: np.ndarray, counters, seed: int) -> np.ndarray:
+    """Inverse-CDF draws for shots with explicit generator counters."""
+    n = _check_state(psi)
+    cnt = np.ascontiguousarray(np.asarray(counters, dtype=np.uint64))
+    out = np.empty(cnt.size, dtype=np.uint64)
+    F = np.empty(psi.size, dtype=np.float64)
+    lib().or_sample_at(_ptr(psi), n, int(cnt.size), seed & (2**64 - 1), _ptr(cnt), _ptr(out), _ptr(F))
+    return out
+
+
+def qubit_probs(psi: np.ndarray, q: int):
+    """(p0, p1): probability of qubit q reading 0 / 1, Neumaier sums in index order."""
+    n = _check_state(psi)
+    p0, p1 = ctypes.c_double(), ctypes.c_double()
+    lib().or_qubit_probs(_ptr(psi), n, int(q), ctypes.byref(p0), ctypes.byref(p1))
+    return p0.value, p1.value
+
+
+def collapse(psi: np.ndarray, q: int, m: int, pm: float, reset: bool = False):
+    """Project qubit q on outcome m (probability pm) in place; reset returns it to |0>."""
+    n = _check_state(psi)
+    lib().or_collapse(_ptr(psi), n, int(q), int(m), float(pm), int(bool(reset)))
+    return psi
+
+
+def run_shots(ops, n: int, shots: int, seed: int, basis: int = 0, psi: np.ndarray | None = None):
+    """Every shot simulated on its own from the start (Sec. III-B: with
+    mid-circuit measurements or resets each shot is its own trajectory).
+    ops may hold ("measure", (qubit, clbit), ()) and ("reset", (qubit,), ()).
+    At the k-th measure/reset (k = 0..K-1 in list order) shot s draws
+    u = U01(seed, s*(K+1) + k), the qubit reads 1 exactly when u*(p0+p1) >= p0,
+    and the state is projected and rescaled; the terminal sample of all qubits
+    uses counter s*(K+1) + K. Returns (clbits, samples), one entry per shot."""
+    K = sum(1 for o in ops if o[0] in ("measure", "reset"))
+    start = basis_state(n, basis) if psi is None else psi
+    clbits = np.zeros(shots, dtype=np.uint64)
+    samples = np.zeros(shots, dtype=np.uint64)
+    for s in range(shots):
+        st = start.copy()
+        k = 0
+        for op in ops:
+            if op[0] in ("measure", "reset"):
+                q = int(op[1][0])
+                p0, p1 = qubit_probs(st, q)
+                u = u01(seed, s * (K + 1) + k)
+                m = 1 if u * (p0 + p1) >= p0 else 0
+                collapse(st, q, m, p1 if m else p0, reset=(op[0] == "reset"))
+                if op[0] == "measure":
+                    b = np.uint64(1) << np.uint64(op[1][1])
+                    clbits[s] = (clbits[s] | b) if m else (clbits[s] & ~b)
+                k += 1
+            else:
+                apply_op(st, op)
+        samples[s] = sample_at(st, [s * (K + 1) + K], seed)[0]
+    return clbits, samples
 
 
 def expect(psi: np.ndarray, xmask: int, zmask: int):

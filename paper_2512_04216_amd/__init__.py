@@ -15,7 +15,8 @@ import numpy as np
 
 from . import _abi
 from ._abi import (  # noqa: F401
-    GATE_KIND, GATE_KINDS, SV_C64, SV_C128, SV_FUSE_TILED, SV_OP_ADJOINT, SvError, check, load, sv_op, sv_pauli,
+    GATE_KIND, GATE_KINDS, OP_KIND, SV_C64, SV_C128, SV_FUSE_TILED, SV_OP_ADJOINT, SvError, check, load, sv_op,
+    sv_pauli,
 )
 
 __all__ = ["Context", "State", "Server", "ops_to_array", "terms_to_array", "SvError", "load",
@@ -41,7 +42,7 @@ def ops_to_numpy(ops) -> np.ndarray:
     """Gate list [(name, qubits, params[, adjoint])] -> numpy array laid out as sv_op."""
     a = np.zeros(max(1, len(ops)), dtype=SV_OP_DTYPE)
     for i, op in enumerate(ops):
-        a["kind"][i] = GATE_KIND[op[0]]
+        a["kind"][i] = OP_KIND[op[0]]
         if len(op) > 3 and op[3]:
             a["flags"][i] = SV_OP_ADJOINT
         q = op[1]
@@ -227,6 +228,18 @@ class State:
             raise TypeError("op arrays must use SV_OP_DTYPE")
         check(lib().sv_run(self.handle, arr, len(ops), int(fuse_k)))
         return self
+
+    def run_shots(self, ops, shots: int, seed: int, fuse_k: int = 0, samples: bool = True):
+        """Run a circuit that may hold ("measure", (qubit, clbit), ()) and
+        ("reset", (qubit,), ()) ops once per shot (sv_run_shots). Returns
+        (clbits, samples) as uint64 arrays (samples None if not asked for)."""
+        arr = ops_to_array(ops)
+        cl = np.zeros(max(1, shots), dtype=np.uint64)
+        sm = np.zeros(max(1, shots), dtype=np.uint64) if samples else None
+        U64P = ctypes.POINTER(ctypes.c_uint64)
+        check(lib().sv_run_shots(self.handle, arr, len(ops), int(fuse_k), int(shots), int(seed) & (2**64 - 1),
+                                 cl.ctypes.data_as(U64P), sm.ctypes.data_as(U64P) if samples else None))
+        return cl[:shots], (sm[:shots] if samples else None)
 
     def norm2(self) -> float:
         v = ctypes.c_double()

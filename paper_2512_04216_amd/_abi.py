@@ -26,6 +26,9 @@ STATUS_NAMES = {0: "SV_OK", 1: "SV_PENDING", -1: "SV_E_INVALID", -2: "SV_E_OOM",
 GATE_KINDS = ["h", "x", "y", "z", "s", "sdg", "t", "tdg", "sx", "rx", "ry", "rz", "p", "u3",
               "cx", "cy", "cz", "cp", "swap", "rzz", "ccx"]
 GATE_KIND = {name: i for i, name in enumerate(GATE_KINDS)}
+# non-unitary op kinds (sv_run_shots only)
+SV_OP_MEASURE, SV_OP_RESET = 64, 65
+OP_KIND = dict(GATE_KIND, measure=SV_OP_MEASURE, reset=SV_OP_RESET)
 
 
 class sv_ctx_opts(ctypes.Structure):
@@ -100,6 +103,7 @@ PROTOTYPES = {
     "sv_run": [P, ctypes.POINTER(sv_op), I32, I32],
     "sv_plan_fusion": [ctypes.POINTER(sv_op), I32, I32, I32, IP, IP],
     "sv_plan_passes": [ctypes.POINTER(sv_op), I32, I32, I32, IP],
+    "sv_run_shots": [P, ctypes.POINTER(sv_op), I32, I32, I64, U64, U64P, U64P],
     "sv_norm": [P, DP],
     "sv_renormalize": [P],
     "sv_sample": [P, I64, U64, U64P],

@@ -310,6 +310,62 @@ sv_status run_tiled(sv_state st, const sv_op *ops, int nops, After &after) {
     return r;
 }
 
+// ---- shots with mid-circuit measurements ------------------------------------
+// The generator of the sampler (SplitMix64 at counter s, 53-bit uniform).
+static double host_u01(uint64_t seed, uint64_t s) {
+    uint64_t z = seed + (s + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * 0x1.0p-53;
+}
+
+struct ShotScratch {
+    uint64_t *hmask = nullptr;   // pinned: 1 mask, then 2 results
+    double *hres = nullptr;
+    uint64_t *dmask = nullptr;   // device
+    double *dres = nullptr;
+    uint64_t *dcnt = nullptr, *dout = nullptr;   // device: counters and samples of one branch
+    uint64_t *hcnt = nullptr, *hout = nullptr;   // pinned
+};
+
+// FP64 probabilities of qubit q being 0 / 1 (the compensated Z pass gives
+// p0 - p1 and p0 + p1).
+static sv_status qubit_probs(sv_state st, int q, ShotScratch &w, double *p0, double *p1) {
+    w.hmask[0] = 1ull << q;
+    SV_HIP(hipMemcpyAsync(w.dmask, w.hmask, 8, hipMemcpyHostToDevice, st->stream));
+    SV_HIP(svk::launch_expect_z(st->psi, st->n, st->is_c64(), w.dmask, 1, st->ws, w.dres, st->stream));
+    SV_HIP(hipMemcpyAsync(w.hres, w.dres, 16, hipMemcpyDeviceToHost, st->stream));
+    SV_HIP(hipStreamSynchronize(st->stream));
+    const double z = w.hres[0], tot = w.hres[1];
+    *p0 = std::min(tot, std::max(0.0, 0.5 * (tot + z)));
+    *p1 = std::min(tot, std::max(0.0, 0.5 * (tot - z)));
+    return SV_OK;
+}
+
+// Project qubit q on outcome m and rescale by 1/sqrt(pm); with `reset` an
+// outcome 1 is moved back to |0>.
+static sv_status collapse(sv_state st, int q, int m, double pm, bool reset) {
+    const double c = 1.0 / std::sqrt(pm);
+    TraceScope ts(&st->ctx->tracer, st->stream, "collapse", 2.0 * (double)st->bytes);
+    if (reset && m == 1) {
+        svk::GroupGate g;   // members (q = 0, q = 1): new a0 = c a1, new a1 = 0
+        g.fm = 1ull << q;
+        g.fv = 0;
+        g.K = 1;
+        g.F[0] = 1ull << q;
+        g.U[2] = c;
+        SV_HIP(svk::launch_group(g, st->psi, st->n, st->is_c64(), st->stream));
+    } else {
+        svk::DiagGate d;
+        d.k = 1;
+        d.targets[0] = q;
+        d.d[2 * m] = c;
+        SV_HIP(svk::launch_diag(d, st->psi, st->n, st->is_c64(), st->stream));
+    }
+    return SV_OK;
+}
+
 }  // namespace svh
 
 using namespace svh;
@@ -576,6 +632,154 @@ sv_status sv_plan_passes(const sv_op *ops, int nops, int n, sv_dtype dt, int *np
     const int is_c64 = dt == SV_C64 ? 1 : 0;
     *npasses = tops.empty() ? 0 : (int)plan_passes(tops, n, svk::tile_bits(is_c64), svk::low_bits(is_c64)).size();
     return SV_OK;
+}
+
+sv_status sv_run_shots(sv_state st, const sv_op *ops, int nops, int fuse_k, int64_t shots, uint64_t seed,
+                       uint64_t *clbits_out, uint64_t *samples_out) {
+    if (!st || (!ops && nops) || nops < 0 || shots < 0) return fail(SV_E_INVALID, "bad argument");
+    if (shots > 0 && !clbits_out) return fail(SV_E_INVALID, "null clbits_out");
+    if (fuse_k != 0 && fuse_k != SV_FUSE_TILED && (fuse_k < 2 || fuse_k > SV_MAX_FUSED))
+        return fail(SV_E_INVALID, "fuse_k must be 0, 2..5 or SV_FUSE_TILED");
+    int K = 0;
+    for (int i = 0; i < nops; ++i) {
+        const sv_op &o = ops[i];
+        if (o.kind == SV_OP_MEASURE || o.kind == SV_OP_RESET) {
+            if (o.q[0] < 0 || o.q[0] >= st->n) return fail(SV_E_INVALID, "op " + std::to_string(i) + ": qubit out of range");
+            if (o.kind == SV_OP_MEASURE && (o.q[1] < 0 || o.q[1] > 63))
+                return fail(SV_E_INVALID, "op " + std::to_string(i) + ": classical bit out of range 0..63");
+            ++K;
+        } else {
+            sv_status r = validate_ops(st, &o, 1);
+            if (r) return r;
+        }
+    }
+    if (shots == 0) return SV_OK;
+    for (int64_t s = 0; s < shots; ++s) clbits_out[s] = 0;
+    auto unitary_end = [&](int i) {
+        while (i < nops && ops[i].kind != SV_OP_MEASURE && ops[i].kind != SV_OP_RESET) ++i;
+        return i;
+    };
+    sv_ctx c = st->ctx;
+    ShotScratch w;
+    sv_status r = SV_OK;
+    char *pin = nullptr;
+    const uint64_t nsh = (uint64_t)shots;
+    if (hipHostMalloc((void **)&pin, 64 + 16 * nsh, hipHostMallocDefault) != hipSuccess)
+        return fail(SV_E_OOM, "pinned scratch for the shots");
+    w.hmask = (uint64_t *)pin;
+    w.hres = (double *)(pin + 16);
+    w.hcnt = (uint64_t *)(pin + 64);
+    w.hout = w.hcnt + nsh;
+    char *dev = (char *)c->arena.alloc(64 + 16 * nsh);
+    if (!dev) {
+        hipHostFree(pin);
+        return fail(SV_E_OOM, "arena cannot hold the shot scratch");
+    }
+    w.dmask = (uint64_t *)dev;
+    w.dres = (double *)(dev + 16);
+    w.dcnt = (uint64_t *)(dev + 64);
+    w.dout = w.dcnt + nsh;
+
+    struct Branch {
+        sv_state st;
+        bool own;
+        std::vector<int64_t> shots;
+        int op, k;
+    };
+    std::vector<Branch> stack;
+    {
+        Branch b{st, false, {}, 0, 0};
+        b.shots.resize(nsh);
+        for (int64_t s = 0; s < shots; ++s) b.shots[s] = s;
+        stack.push_back(std::move(b));
+    }
+    auto drop = [&](Branch &b) {
+        if (b.own) {
+            hipStreamSynchronize(b.st->stream);
+            state_release(b.st);
+            b.st = nullptr;
+        }
+    };
+    while (!stack.empty() && r == SV_OK) {
+        Branch b = std::move(stack.back());
+        stack.pop_back();
+        while (r == SV_OK) {
+            if (b.op < nops && ops[b.op].kind != SV_OP_MEASURE && ops[b.op].kind != SV_OP_RESET) {
+                const int e = unitary_end(b.op);
+                r = sv_run(b.st, ops + b.op, e - b.op, fuse_k);
+                b.op = e;
+                continue;
+            }
+            if (b.op == nops) {
+                // terminal draws of this branch's shots
+                if (samples_out) {
+                    const uint64_t cnt = b.shots.size();
+                    for (uint64_t i = 0; i < cnt; ++i) w.hcnt[i] = (uint64_t)b.shots[i] * (uint64_t)(K + 1) + (uint64_t)K;
+                    hipError_t he = hipMemcpyAsync(w.dcnt, w.hcnt, 8 * cnt, hipMemcpyHostToDevice, b.st->stream);
+                    if (he == hipSuccess) he = svk::launch_cdf(b.st->psi, b.st->n, b.st->is_c64(), b.st->ws, b.st->stream);
+                    if (he == hipSuccess)
+                        he = svk::launch_sample_at(b.st->psi, b.st->n, b.st->is_c64(), b.st->ws, (int64_t)cnt, seed, 0,
+                                                   w.dcnt, w.dout, b.st->stream);
+                    if (he == hipSuccess) he = hipMemcpyAsync(w.hout, w.dout, 8 * cnt, hipMemcpyDeviceToHost, b.st->stream);
+                    if (he == hipSuccess) he = hipStreamSynchronize(b.st->stream);
+                    if (he != hipSuccess) r = hip_fail(he, "terminal sampling");
+                    for (uint64_t i = 0; i < cnt && r == SV_OK; ++i) samples_out[b.shots[i]] = w.hout[i];
+                }
+                break;
+            }
+            // measurement or reset
+            const sv_op &o = ops[b.op];
+            const int q = o.q[0];
+            double p0, p1;
+            r = qubit_probs(b.st, q, w, &p0, &p1);
+            if (r) break;
+            const double tot = p0 + p1;
+            if (!(tot > 0.0)) {
+                r = fail(SV_E_NUMERIC, "state has zero norm at a measurement");
+                break;
+            }
+            std::vector<int64_t> g0, g1;
+            for (int64_t s : b.shots) {
+                const double u = host_u01(seed, (uint64_t)s * (uint64_t)(K + 1) + (uint64_t)b.k);
+                (u * tot >= p0 ? g1 : g0).push_back(s);
+            }
+            if (o.kind == SV_OP_MEASURE) {
+                const uint64_t bit = 1ull << o.q[1];
+                for (int64_t s : g0) clbits_out[s] &= ~bit;
+                for (int64_t s : g1) clbits_out[s] |= bit;
+            }
+            const bool reset = o.kind == SV_OP_RESET;
+            if (!g0.empty() && !g1.empty()) {
+                // the shots disagree: clone the state for outcome 1, keep this one for outcome 0
+                sv_state cl = nullptr;
+                r = state_create(c, b.st->n, b.st->dtype, b.st->stream, &cl);
+                if (r) break;
+                hipError_t he = hipMemcpyAsync(cl->psi, b.st->psi, b.st->bytes, hipMemcpyDeviceToDevice, b.st->stream);
+                if (he != hipSuccess) {
+                    hipStreamSynchronize(b.st->stream);
+                    state_release(cl);
+                    r = hip_fail(he, "state clone");
+                    break;
+                }
+                r = collapse(cl, q, 1, p1, reset);
+                stack.push_back(Branch{cl, true, std::move(g1), b.op + 1, b.k + 1});
+                if (r) break;
+                r = collapse(b.st, q, 0, p0, reset);
+                b.shots = std::move(g0);
+            } else {
+                const int m = g1.empty() ? 0 : 1;
+                r = collapse(b.st, q, m, m ? p1 : p0, reset);
+            }
+            b.op += 1;
+            b.k += 1;
+        }
+        drop(b);
+    }
+    for (Branch &b : stack) drop(b);
+    hipStreamSynchronize(st->stream);
+    c->arena.free(dev);
+    hipHostFree(pin);
+    return r;
 }
 
 sv_status sv_plan_fusion(const sv_op *ops, int nops, int n, int fuse_k, int *nblocks, int *nsingle) {

@@ -210,11 +210,13 @@ __device__ inline double read_lane_d(double v, int l) {
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_sample(const u4 *__restrict__ psi, int n, const double *__restrict__ leafcdf,
-                                                int64_t shots, uint64_t seed, uint64_t s0, uint64_t *__restrict__ out) {
+                                                int64_t shots, uint64_t seed, uint64_t s0,
+                                                const uint64_t *__restrict__ counters, uint64_t *__restrict__ out) {
     constexpr int E = Amp<T>::E;
     const uint64_t sl = wave_id_global();
     if (sl >= (uint64_t)shots) return;
-    const uint64_t s = s0 + sl;
+    // generator counter of this shot: s0 + its position, or given explicitly
+    const uint64_t s = counters ? counters[sl] : s0 + sl;
     const int lane = threadIdx.x & 63;
     const uint64_t nleaf = nleaf_of(n);
     const double total = leafcdf[nleaf];
@@ -549,16 +551,21 @@ hipError_t launch_norm(const void *psi, int n, int is_c64, void *ws, hipStream_t
 
 hipError_t launch_sample(const void *psi, int n, int is_c64, const void *ws, int64_t shots, uint64_t seed,
                          uint64_t s0, uint64_t *out_dev, hipStream_t s) {
+    return launch_sample_at(psi, n, is_c64, ws, shots, seed, s0, nullptr, out_dev, s);
+}
+
+hipError_t launch_sample_at(const void *psi, int n, int is_c64, const void *ws, int64_t shots, uint64_t seed,
+                            uint64_t s0, const uint64_t *counters_dev, uint64_t *out_dev, hipStream_t s) {
     if (shots <= 0) return hipSuccess;
     const WS w = ws_layout(n);
     const double *d = wsd(ws);
     const unsigned blocks = (unsigned)((shots + 3) / 4);
     if (is_c64)
         hipLaunchKernelGGL(k_sample<float>, dim3(blocks), dim3(256), 0, s, (const u4 *)psi, n, d + w.off_leafcdf, shots,
-                           seed, s0, out_dev);
+                           seed, s0, counters_dev, out_dev);
     else
         hipLaunchKernelGGL(k_sample<double>, dim3(blocks), dim3(256), 0, s, (const u4 *)psi, n, d + w.off_leafcdf,
-                           shots, seed, s0, out_dev);
+                           shots, seed, s0, counters_dev, out_dev);
     return hipGetLastError();
 }
 

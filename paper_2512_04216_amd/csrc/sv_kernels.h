@@ -130,6 +130,9 @@ hipError_t launch_norm(const void *psi, int n, int is_c64, void *ws, hipStream_t
 // Shots s0 .. s0+shots-1 (the counter of the generator), results to out_dev[0..shots).
 hipError_t launch_sample(const void *psi, int n, int is_c64, const void *ws, int64_t shots,
                          uint64_t seed, uint64_t s0, uint64_t *out_dev, hipStream_t s);
+// The same with shot i drawing generator counter counters_dev[i] (device array of `shots`).
+hipError_t launch_sample_at(const void *psi, int n, int is_c64, const void *ws, int64_t shots, uint64_t seed,
+                            uint64_t s0, const uint64_t *counters_dev, uint64_t *out_dev, hipStream_t s);
 // Z-only Pauli batch (nterms <= 64): out_dev[t] = sum_i (-1)^{popc(i & z_t)} |psi_i|^2
 // (unnormalised) for t < nterms, out_dev[nterms] = sum_i |psi_i|^2.
 hipError_t launch_expect_z(const void *psi, int n, int is_c64, const uint64_t *zmasks,

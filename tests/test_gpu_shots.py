@@ -1,0 +1,81 @@
+"""GPU parity of shots with mid-circuit measurements and resets
+(sv_run_shots) against the oracle's per-shot trajectories: the same classical
+bits and terminal samples for every shot, through per-gate, fused and tiled
+runs between the measurements, complex128 and complex64."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def with_measurements(n, ngates, nmeas, seed):
+    """A random circuit with `nmeas` measurements (into clbits 0..) and resets
+    at random positions."""
+    rng = np.random.default_rng(seed)
+    ops = W.random_circuit(n, ngates, seed=seed)
+    pos = sorted(rng.choice(ngates + 1, size=nmeas, replace=True))
+    out, c = [], 0
+    for i in range(ngates + 1):
+        while pos and pos[0] == i:
+            pos.pop(0)
+            q = int(rng.integers(0, n))
+            if rng.random() < 0.7:
+                out.append(("measure", (q, c % 64), ()))
+                c += 1
+            else:
+                out.append(("reset", (q,), ()))
+        if i < ngates:
+            out.append(ops[i])
+    return out
+
+
+@pytest.mark.parametrize("fuse_k", [0, 5, -1])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [3, 8, 15])
+def test_shots_match_oracle_trajectories(ctx, S, O, n, dtype, fuse_k):
+    shots = 200
+    ops = with_measurements(n, 60 if n < 10 else 120, 6, seed=100 * n + 7)
+    want_cl, want_sm = O.run_shots(ops, n, shots, seed=555)
+    with S.State(ctx, n, dtype) as st:
+        cl, sm = st.run_shots(ops, shots, 555, fuse_k=fuse_k)
+    # an outcome flips only if a draw lands within rounding of p0: a shot that
+    # differs differs from there on, so compare whole shots
+    bad = np.count_nonzero((cl != want_cl) | (sm != want_sm))
+    assert bad <= (1 if dtype == "c128" else max(2, shots // 50))
+    assert np.all(sm < (1 << n))
+
+
+def test_no_measurements_equals_sampling(ctx, S):
+    n = 12
+    ops = W.random_circuit(n, 80, seed=5)
+    with S.State(ctx, n, "c128") as st:
+        st.run(ops)
+        direct = st.sample(1000, 77)
+        st.reset(0)
+        cl, sm = st.run_shots(ops, 1000, 77)
+    assert np.array_equal(sm, direct) and not cl.any()
+
+
+def test_measure_ops_rejected_outside_run_shots(ctx, S):
+    with S.State(ctx, 4, "c128") as st:
+        with pytest.raises(S.SvError):
+            st.run([("h", (0,), ()), ("measure", (0, 0), ())])
+        with pytest.raises(S.SvError):
+            st.run_shots([("measure", (0, 64), ())], 4, 1)     # classical bit out of range
+        with pytest.raises(S.SvError):
+            st.run_shots([("reset", (4,), ())], 4, 1)          # qubit out of range
+
+
+def test_branches_at_24_qubits(ctx, S):
+    # GHZ on 24 qubits, then measurements of 5 qubits that split the shots:
+    # each shot's bits all equal its first outcome, and branches are cloned
+    n, shots = 24, 64
+    ops = W.ghz(n) + [("measure", (q, i), ()) for i, q in enumerate((0, 5, 11, 17, 23))]
+    with S.State(ctx, n, "c128") as st:
+        cl, sm = st.run_shots(ops, shots, 1234)
+    first = cl & np.uint64(1)
+    assert np.array_equal(cl, first * np.uint64(31))
+    assert np.array_equal(sm, first * np.uint64((1 << n) - 1))
+    assert 0 < int(first.sum()) < shots

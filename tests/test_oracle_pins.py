@@ -349,3 +349,67 @@ def test_qaoa_p1_closed_form(O, seed):
     want = qaoa_p1_edge_zz(gamma, beta, edges, n)
     assert np.max(np.abs(vals - want)) <= 1e-13
     assert abs(energy - want.sum()) <= 1e-12
+
+
+# ---- mid-circuit measurement and reset (per-shot trajectories) ------------------
+
+def test_shots_without_measurements_equal_terminal_sampling(O):
+    # with no measure/reset every shot uses counter s, the plain sampler's draw
+    ops = W.random_circuit(5, 40, seed=3)
+    psi = O.run(ops, 5)
+    cl, sm = O.run_shots(ops, 5, 200, seed=11)
+    assert np.array_equal(sm, O.sample(psi, 200, 11)) and not cl.any()
+
+
+def test_measuring_a_basis_state_is_deterministic(O):
+    n, b = 6, 0b101101
+    ops = [("x", (q,), ()) for q in range(n) if (b >> q) & 1]
+    ops += [("measure", (q, 5 - q), ()) for q in range(n)]
+    cl, sm = O.run_shots(ops, n, 64, seed=5)
+    rev = int("".join(str((b >> q) & 1) for q in range(n)), 2)   # clbit 5 - q holds qubit q
+    assert np.all(cl == rev) and np.all(sm == b)
+
+
+def test_ghz_measurement_fixes_every_qubit(O):
+    n, S = 5, 2000
+    ops = W.ghz(n) + [("measure", (0, 0), ())]
+    cl, sm = O.run_shots(ops, n, S, seed=9)
+    ones = int(cl.sum())
+    assert np.all(sm == np.where(cl == 1, (1 << n) - 1, 0))      # collapse of every qubit
+    assert abs(ones - S / 2) <= 5 * math.sqrt(S / 4)               # P(1) = 1/2
+
+
+def test_repeated_measurement_repeats_and_reset_zeroes(O):
+    n, S = 4, 500
+    ops = W.random_circuit(n, 30, seed=21) + [("measure", (2, 0), ()), ("measure", (2, 1), ()),
+                                              ("reset", (3,), ()), ("measure", (3, 2), ())]
+    cl, sm = O.run_shots(ops, n, S, seed=13)
+    assert np.array_equal(cl & 1, (cl >> np.uint64(1)) & np.uint64(1))   # same outcome twice
+    assert not ((cl >> np.uint64(2)) & np.uint64(1)).any()                 # reset qubit reads 0
+    assert not (sm & np.uint64(8)).any()
+    assert np.array_equal((sm >> np.uint64(2)) & np.uint64(1), cl & np.uint64(1))
+
+
+@pytest.mark.parametrize("theta", [0.3, 1.1, 2.6])
+def test_born_rule_frequency(O, theta):
+    S = 4000
+    cl, _ = O.run_shots([("ry", (0,), (theta,)), ("measure", (0, 0), ())], 2, S, seed=17)
+    p1 = math.sin(theta / 2) ** 2
+    assert abs(int(cl.sum()) - S * p1) <= 5 * math.sqrt(S * p1 * (1 - p1))
+
+
+def test_untouched_measured_qubit_keeps_its_outcome(O):
+    # measuring qubit 1 and then running gates that avoid it: the terminal
+    # sample keeps the measured bit, and the other qubits' joint distribution is
+    # that of the unmeasured circuit (the measurement commutes with them)
+    n, S = 4, 4000
+    pre = W.random_circuit(n, 30, seed=31)
+    post = [o for o in W.random_circuit(n, 60, seed=32) if 1 not in o[1]]
+    cl, sm = O.run_shots(pre + [("measure", (1, 0), ())] + post, n, S, seed=19)
+    assert np.array_equal((sm >> np.uint64(1)) & np.uint64(1), cl)
+    psi = O.run(pre + post, n)
+    p = np.abs(psi) ** 2
+    marg = np.array([p[[i for i in range(1 << n) if (i & ~2) == k]].sum() for k in range(1 << n) if not k & 2])
+    got = np.bincount([int(x) & ~2 for x in sm], minlength=1 << n)[[k for k in range(1 << n) if not k & 2]] / S
+    K = len(marg)
+    assert 0.5 * np.abs(got - marg).sum() <= 0.5 * math.sqrt((K - 1) / S) + math.sqrt(math.log(1e6) / (2 * S))
