@@ -278,6 +278,61 @@ def bench_qaoa(S):
     return out
 
 
+def bench_small(S, reps=200, batch=2000):
+    """12-qubit brickwork, 20 layers (350 gates), complex128, 1024 shots: a
+    latency-bound circuit (the whole state is 64 KiB). Microseconds per
+    circuit (run + shots, host-synchronous) one kernel per gate, in fused
+    blocks, in tiled passes (one launch: the circuit fits one tile), and
+    through the server's packed LDS kernel: one request alone, and `batch`
+    requests at once (many circuits per launch)."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+
+    n, shots = 12, 1024
+    ops = W.brickwork(n, 20, seed=SEED - 1)
+    arr = S.ops_to_numpy(ops)
+    ctx = S.Context(arena_bytes=8 << 30)
+    out = {"gates": len(ops), "shots": shots}
+    st = S.State(ctx, n, "c128")
+    for fk, key in ((0, "per_gate"), (5, "fused"), (S.SV_FUSE_TILED, "tiled")):
+        for _ in range(5):
+            st.reset(0)
+            st.run(arr, fuse_k=fk)
+            st.sample(shots, SEED)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r in range(reps):
+            st.reset(0)
+            st.run(arr, fuse_k=fk)
+            st.sample(shots, SEED + r)
+        dt = (time.perf_counter() - t0) / reps
+        out[key] = {"us_per_circuit": round(dt * 1e6, 1)}
+        print("bench small: %s %.1f us" % (key, dt * 1e6), file=sys.stderr, flush=True)
+    out["tiled"]["launches_for_gates"] = S.sv_plan_passes(ops, n, "c128")
+    st.close()
+    with S.Server(ctx) as srv:
+        for _ in range(5):
+            srv.wait(srv.submit(n, arr, shots=shots, seed=SEED, dtype="c128"), 60000)
+        lat = []
+        for r in range(100):
+            res = srv.wait(srv.submit(n, arr, shots=shots, seed=SEED + r, dtype="c128"), 60000)
+            lat.append((res["t_done_ns"] - res["t_submit_ns"]) / 1e3)
+        out["server_alone"] = {"p50_us": round(float(np.percentile(lat, 50)), 1),
+                               "p99_us": round(float(np.percentile(lat, 99)), 1)}
+        t0 = time.perf_counter()
+        ids = [srv.submit(n, arr, shots=shots, seed=SEED + r, dtype="c128") for r in range(batch)]
+        res = [srv.wait(i, 60000) for i in ids]
+        dt = time.perf_counter() - t0
+        st_ = srv.stats()
+        out["server_batch"] = {"circuits": batch, "circuits_per_s": round(batch / dt, 1),
+                               "us_per_circuit": round(dt / batch * 1e6, 2), "packed_launches": st_["packed_launches"]}
+        assert all(x["status"] == 0 for x in res)
+    ctx.close()
+    return out
+
+
 def bench_serving(S, count=10000, baseline_count=300, loads=(0.5, 0.8, 0.95)):
     """Serving stream: `count` circuits, n uniform 8..26, depth uniform 5..40,
     gates uniform from {H,S,T,RX,RY,RZ,CNOT,CZ,SWAP}, 1000 shots, complex64.
@@ -363,7 +418,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c64", action="store_true", help="skip the complex64 side measurement")
     ap.add_argument("--no-trace", action="store_true")
-    ap.add_argument("--config", default="28q", choices=["28q", "fused", "qaoa", "serving"],
+    ap.add_argument("--config", default="28q", choices=["28q", "small", "fused", "qaoa", "serving"],
                     help="28q (default): the headline line; the others print their own JSON line")
     ap.add_argument("--serving-count", type=int, default=10000)
     args = ap.parse_args()
@@ -379,7 +434,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.config != "28q":
         fn = {"fused": lambda: bench_fused(S), "qaoa": lambda: bench_qaoa(S),
-              "serving": lambda: bench_serving(S, count=args.serving_count)}[args.config]
+              "serving": lambda: bench_serving(S, count=args.serving_count),
+              "small": lambda: bench_small(S)}[args.config]
         print(json.dumps({"config": args.config, "result": fn()}))
         return
     print("bench: 28-qubit brickwork + QFT, %s, %d warmup + %d timed steps" % (args.dtype, args.warmup, args.steps),

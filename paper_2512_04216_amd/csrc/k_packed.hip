@@ -11,6 +11,8 @@
 #include "sv_device.h"
 #include "sv_kernels.h"
 
+#include <atomic>
+
 #include <algorithm>
 
 using namespace svd;
@@ -207,6 +209,8 @@ __global__ __launch_bounds__(kThreads) void k_packed(svk::PackedBatch b) {
 
 namespace svk {
 
+int packed_max_qubits(int is_c64) { return is_c64 ? 13 : 12; }
+
 uint64_t packed_lds_bytes(int max_qubits, int is_c64) {
     const uint64_t amps = 1ull << max_qubits;
     const uint64_t leaves = max_qubits > 6 ? amps >> 6 : 1;
@@ -216,8 +220,21 @@ uint64_t packed_lds_bytes(int max_qubits, int is_c64) {
 
 hipError_t launch_packed(const PackedBatch &b, int is_c64, int max_qubits, int max_blocks, hipStream_t s) {
     if (b.ncirc <= 0) return hipSuccess;
+    if (max_qubits > packed_max_qubits(is_c64)) return hipErrorInvalidValue;
     const unsigned blocks = (unsigned)std::min(b.ncirc, std::max(1, max_blocks));
     const size_t lds = (size_t)packed_lds_bytes(max_qubits, is_c64);
+    // states of 2^12 complex128 / 2^13 complex64 amplitudes need more than the
+    // default 64 KiB of dynamic LDS (gfx950 has 160 KiB per workgroup)
+    static std::atomic<bool> attr_set[2] = {false, false};
+    if (!attr_set[is_c64 ? 1 : 0].load(std::memory_order_acquire)) {
+        const int most = (int)packed_lds_bytes(packed_max_qubits(is_c64), is_c64);
+        hipError_t e = is_c64 ? hipFuncSetAttribute((const void *)k_packed<float>,
+                                                    hipFuncAttributeMaxDynamicSharedMemorySize, most)
+                              : hipFuncSetAttribute((const void *)k_packed<double>,
+                                                    hipFuncAttributeMaxDynamicSharedMemorySize, most);
+        if (e != hipSuccess) return e;
+        attr_set[is_c64 ? 1 : 0].store(true, std::memory_order_release);
+    }
     if (is_c64)
         hipLaunchKernelGGL(k_packed<float>, dim3(blocks), dim3(kThreads), lds, s, b);
     else

@@ -131,7 +131,7 @@ struct sv_server_s {
     uint64_t held = 0, cap = 0;
     int active = 0;
     int rr = 0;
-    int small_c64 = 12, small_c128 = 11;
+    int small_c64 = svk::packed_max_qubits(1), small_c128 = svk::packed_max_qubits(0);
     std::atomic<bool> stop{false};
     std::thread driver;
     sv_server_stats stats{};
@@ -688,8 +688,8 @@ sv_status sv_server_create(sv_ctx ctx, const sv_server_opts *opts, sv_server *ou
     if (s->o.max_queue <= 0) s->o.max_queue = 1 << 20;
     if (s->o.nstreams <= 0) s->o.nstreams = 3;
     if (s->o.small_qubits > 0) {
-        s->small_c64 = std::min(s->o.small_qubits, 12);
-        s->small_c128 = std::min(s->o.small_qubits, 11);
+        s->small_c64 = std::min(s->o.small_qubits, svk::packed_max_qubits(1));
+        s->small_c128 = std::min(s->o.small_qubits, svk::packed_max_qubits(0));
     }
     s->cap = s->o.arena_bytes ? std::min<uint64_t>(s->o.arena_bytes, ctx->arena.size()) : ctx->arena.size();
     const uint64_t pinned_bytes = 256ull << 20;

@@ -174,6 +174,9 @@ struct PackedBatch {
     double *res;
 };
 
+// Largest circuit of the packed kernel: 12 qubits complex128, 13 complex64
+// (the state plus leaf sums in one workgroup's LDS).
+int packed_max_qubits(int is_c64);
 uint64_t packed_lds_bytes(int max_qubits, int is_c64);
 hipError_t launch_packed(const PackedBatch &b, int is_c64, int max_qubits, int max_blocks, hipStream_t s);
 
