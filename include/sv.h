@@ -162,6 +162,10 @@ sv_status sv_gate_matrix(int kind, const double *params, int adjoint, double *U_
 
 /* sv_run / sv_circuit fuse_k value: multi-gate passes over LDS tiles. */
 #define SV_FUSE_TILED (-1)
+/* sv_run / sv_circuit fuse_k value: the mode (0, 5 or SV_FUSE_TILED) with the
+ * smallest time predicted by the context's cost model (sv_ctx_set_cost_model);
+ * SV_FUSE_TILED when the context has none. */
+#define SV_FUSE_AUTO (-2)
 
 /* Run a gate list in order (the state-vector method, Sec. II: one update of
  * the amplitude vector per gate). fuse_k = 0 launches one kernel per gate;
@@ -259,6 +263,52 @@ sv_status sv_trace_enable(sv_ctx ctx, int on);
 /* Waits for outstanding traced work, fills up to cap records, sets *count to the
  * number of classes seen, and clears the counters. */
 sv_status sv_trace_read(sv_ctx ctx, sv_trace_rec *out, int cap, int *count);
+
+/* ---------------------------------------------------------- cost model */
+
+/* Runtime prediction by a sum of calibrated operation costs (Sec. III-C,
+ * Eq. (1)): T = sum over the operations a run launches of C_class(n), plus
+ * C_CDF(n) + S * C_SHOT(n) for S shots (the linear shot model c1 + c2 S).
+ * C_class(n) is a per-class curve over the qubit count, known at the
+ * calibrated n and interpolated between them by piecewise cubic Hermite
+ * interpolation (Fritsch-Carlson monotone slopes) of log2 C; beyond the
+ * calibrated range it scales as 2^n from the nearest end. Classes: */
+enum {
+    SV_COST_GATE_FULL = 0,   /* per-gate sweep touching every amplitude (dense 1q/2q, two-level) */
+    SV_COST_GATE_HALF,       /* per-gate sweep touching half (CX, SWAP, S, T, P, Z, ...) */
+    SV_COST_GATE_QUARTER,    /* per-gate sweep touching a quarter or less (CZ, CP, CCX) */
+    SV_COST_GATE_DIAG,       /* general diagonal gate (RZ, RZZ) */
+    SV_COST_FUSED_BLOCK,     /* one fused block of 3..5 qubits (MFMA kernel) */
+    SV_COST_TILED_PASS,      /* one tiled pass, its load and store */
+    SV_COST_TILED_RECORD,    /* one record inside a tiled pass touching the whole tile */
+    SV_COST_CDF,             /* the FP64 CDF pass before sampling */
+    SV_COST_SHOT,            /* one shot */
+    SV_COST_TILED_RECORD_PART, /* one record inside a tiled pass touching part of the tile
+                                  (a phase, or a gate with a control on a tile qubit) */
+    SV_COST_NCLASS
+};
+typedef struct sv_cost_model_s *sv_cost_model;
+
+/* Calibrate on the device (the paper's one-time benchmark of the host): for
+ * every n in [n_lo, n_hi] (1 <= n_lo <= n_hi, n_hi within the dtype's limit and
+ * the arena) time each class on a synthetic state with HIP events. Takes a few
+ * seconds at n_hi = 28. */
+sv_status sv_cost_calibrate(sv_ctx ctx, sv_dtype dt, int n_lo, int n_hi, sv_cost_model *out);
+/* A model from a table: coef[(n - n_lo) * SV_COST_NCLASS + class] = seconds
+ * (every entry > 0), n in [n_lo, n_hi]. The table is copied. */
+sv_status sv_cost_model_create(sv_dtype dt, int n_lo, int n_hi, const double *coef, sv_cost_model *out);
+/* Copy of the model's table (n_hi - n_lo + 1) * SV_COST_NCLASS entries; n range out. */
+sv_status sv_cost_model_table(sv_cost_model m, int *n_lo, int *n_hi, double *coef_out, int capacity);
+sv_status sv_cost_model_destroy(sv_cost_model m);
+/* C_class(n) at a real n (interpolated / scaled as above). */
+sv_status sv_cost_coefficient(sv_cost_model m, int cls, double n, double *seconds);
+/* Predicted seconds of sv_run(ops, fuse_k) on n qubits plus `shots` shots
+ * (fuse_k 0, 2..5 or SV_FUSE_TILED). */
+sv_status sv_cost_predict(sv_cost_model m, const sv_op *ops, int nops, int n, int fuse_k, int64_t shots,
+                          double *seconds);
+/* Attach a model to a context (borrowed: it must outlive the context's use of
+ * SV_FUSE_AUTO; NULL detaches). */
+sv_status sv_ctx_set_cost_model(sv_ctx ctx, sv_cost_model m);
 
 /* ------------------------------------------------------------- serving */
 

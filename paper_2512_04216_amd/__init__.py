@@ -15,12 +15,12 @@ import numpy as np
 
 from . import _abi
 from ._abi import (  # noqa: F401
-    GATE_KIND, GATE_KINDS, OP_KIND, SV_C64, SV_C128, SV_FUSE_TILED, SV_OP_ADJOINT, SvError, check, load, sv_op,
-    sv_pauli,
+    COST_CLASSES, GATE_KIND, GATE_KINDS, OP_KIND, SV_C64, SV_C128, SV_FUSE_AUTO, SV_FUSE_TILED, SV_OP_ADJOINT,
+    SvError, check, load, sv_op, sv_pauli,
 )
 
 __all__ = ["Context", "State", "Server", "ops_to_array", "terms_to_array", "SvError", "load",
-           "GATE_KIND", "SV_C64", "SV_C128", "SV_FUSE_TILED"]
+           "GATE_KIND", "SV_C64", "SV_C128", "SV_FUSE_TILED", "SV_FUSE_AUTO", "CostModel"]
 
 
 def lib():
@@ -111,6 +111,61 @@ def sv_plan_fusion(ops, n, fuse_k):
     return nb.value, ns.value
 
 
+class CostModel:
+    """Calibrated per-operation cost curves (sv_cost_*): predicts the seconds a
+    gate list takes in each run mode, and picks SV_FUSE_AUTO's mode when
+    attached to a context."""
+
+    def __init__(self, handle, dtype):
+        self.handle = handle
+        self.dtype = dtype
+
+    @classmethod
+    def calibrate(cls, ctx, dtype="c128", n_lo=4, n_hi=26):
+        h = ctypes.c_void_p()
+        check(lib().sv_cost_calibrate(ctx.handle, _dtype_code(dtype), int(n_lo), int(n_hi), ctypes.byref(h)))
+        return cls(h, dtype)
+
+    @classmethod
+    def from_table(cls, dtype, n_lo, n_hi, coef):
+        a = np.ascontiguousarray(np.asarray(coef, dtype=np.float64).reshape(-1))
+        h = ctypes.c_void_p()
+        check(lib().sv_cost_model_create(_dtype_code(dtype), int(n_lo), int(n_hi),
+                                         a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(h)))
+        return cls(h, dtype)
+
+    def table(self):
+        lo, hi = ctypes.c_int(), ctypes.c_int()
+        check(lib().sv_cost_model_table(self.handle, ctypes.byref(lo), ctypes.byref(hi), None, 0))
+        a = np.zeros((hi.value - lo.value + 1, len(COST_CLASSES)), dtype=np.float64)
+        check(lib().sv_cost_model_table(self.handle, None, None, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        a.size))
+        return lo.value, hi.value, a
+
+    def coefficient(self, cls, n):
+        v = ctypes.c_double()
+        k = COST_CLASSES.index(cls) if isinstance(cls, str) else int(cls)
+        check(lib().sv_cost_coefficient(self.handle, k, float(n), ctypes.byref(v)))
+        return v.value
+
+    def predict(self, ops, n, fuse_k=0, shots=0):
+        v = ctypes.c_double()
+        check(lib().sv_cost_predict(self.handle, ops_to_array(ops), len(ops), int(n), int(fuse_k), int(shots),
+                                    ctypes.byref(v)))
+        return v.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            check(lib().sv_cost_model_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Context:
     """A device context: an HBM arena (a torch uint8 tensor unless
     `use_torch=False`) and the HIP stream new states use."""
@@ -142,6 +197,11 @@ class Context:
         check(L.sv_ctx_create(ctypes.byref(opts), ctypes.byref(h)))
         self.handle = h
         self.arena_bytes = int(arena_bytes)
+
+    def set_cost_model(self, model):
+        """Attach a CostModel (kept alive by this context) for SV_FUSE_AUTO; None detaches."""
+        self._cost = model
+        check(lib().sv_ctx_set_cost_model(self.handle, model.handle if model is not None else None))
 
     def free_bytes(self):
         t, l = ctypes.c_uint64(), ctypes.c_uint64()

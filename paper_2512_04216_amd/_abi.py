@@ -18,6 +18,10 @@ SV_C64, SV_C128 = 0, 1
 SV_OP_ADJOINT = 1
 SV_MAX_QUBITS_C64, SV_MAX_QUBITS_C128, SV_MAX_FUSED = 34, 33, 5
 SV_FUSE_TILED = -1
+SV_FUSE_AUTO = -2
+# cost classes (sv.h, SV_COST_*)
+COST_CLASSES = ["gate_full", "gate_half", "gate_quarter", "gate_diag", "fused_block", "tiled_pass",
+                "tiled_record", "cdf", "shot", "tiled_record_part"]
 
 STATUS_NAMES = {0: "SV_OK", 1: "SV_PENDING", -1: "SV_E_INVALID", -2: "SV_E_OOM", -3: "SV_E_DEVICE",
                 -4: "SV_E_NUMERIC", -5: "SV_E_NOTFOUND", -6: "SV_E_BUSY", -7: "SV_E_UNSUPPORTED"}
@@ -104,6 +108,13 @@ PROTOTYPES = {
     "sv_plan_fusion": [ctypes.POINTER(sv_op), I32, I32, I32, IP, IP],
     "sv_plan_passes": [ctypes.POINTER(sv_op), I32, I32, I32, IP],
     "sv_run_shots": [P, ctypes.POINTER(sv_op), I32, I32, I64, U64, U64P, U64P],
+    "sv_cost_calibrate": [P, I32, I32, I32, ctypes.POINTER(P)],
+    "sv_cost_model_create": [I32, I32, I32, DP, ctypes.POINTER(P)],
+    "sv_cost_model_table": [P, IP, IP, DP, I32],
+    "sv_cost_model_destroy": [P],
+    "sv_cost_coefficient": [P, I32, ctypes.c_double, DP],
+    "sv_cost_predict": [P, ctypes.POINTER(sv_op), I32, I32, I32, I64, DP],
+    "sv_ctx_set_cost_model": [P, P],
     "sv_norm": [P, DP],
     "sv_renormalize": [P],
     "sv_sample": [P, I64, U64, U64P],

@@ -638,8 +638,8 @@ sv_status sv_run_shots(sv_state st, const sv_op *ops, int nops, int fuse_k, int6
                        uint64_t *clbits_out, uint64_t *samples_out) {
     if (!st || (!ops && nops) || nops < 0 || shots < 0) return fail(SV_E_INVALID, "bad argument");
     if (shots > 0 && !clbits_out) return fail(SV_E_INVALID, "null clbits_out");
-    if (fuse_k != 0 && fuse_k != SV_FUSE_TILED && (fuse_k < 2 || fuse_k > SV_MAX_FUSED))
-        return fail(SV_E_INVALID, "fuse_k must be 0, 2..5 or SV_FUSE_TILED");
+    if (fuse_k != 0 && fuse_k != SV_FUSE_TILED && fuse_k != SV_FUSE_AUTO && (fuse_k < 2 || fuse_k > SV_MAX_FUSED))
+        return fail(SV_E_INVALID, "fuse_k must be 0, 2..5, SV_FUSE_TILED or SV_FUSE_AUTO");
     int K = 0;
     for (int i = 0; i < nops; ++i) {
         const sv_op &o = ops[i];
@@ -801,10 +801,11 @@ sv_status sv_plan_fusion(const sv_op *ops, int nops, int n, int fuse_k, int *nbl
 
 sv_status sv_run(sv_state st, const sv_op *ops, int nops, int fuse_k) {
     if (!st || (!ops && nops) || nops < 0) return fail(SV_E_INVALID, "bad argument");
-    if (fuse_k != 0 && fuse_k != SV_FUSE_TILED && (fuse_k < 2 || fuse_k > SV_MAX_FUSED))
-        return fail(SV_E_INVALID, "fuse_k must be 0, 2..5 or SV_FUSE_TILED");
+    if (fuse_k != 0 && fuse_k != SV_FUSE_TILED && fuse_k != SV_FUSE_AUTO && (fuse_k < 2 || fuse_k > SV_MAX_FUSED))
+        return fail(SV_E_INVALID, "fuse_k must be 0, 2..5, SV_FUSE_TILED or SV_FUSE_AUTO");
     sv_status r = validate_ops(st, ops, nops);
     if (r) return r;
+    if (fuse_k == SV_FUSE_AUTO) fuse_k = choose_mode(st->ctx, ops, nops, st->n, 0);
     const int R = st->is_c64() ? st->ctx->renorm_period : 0;
     auto after = [&](int sweeps) -> sv_status {
         if (R <= 0) return SV_OK;

@@ -1,0 +1,400 @@
+// cost.cpp -- runtime prediction by calibrated operation costs (Sec. III-C,
+// Eq. (1)): the total time is a sum over the operations a run launches of a
+// per-class coefficient C_class(n), measured on this device for a range of
+// qubit counts and interpolated between them by piecewise cubic Hermite
+// interpolation, plus the linear shot model C_CDF(n) + S * C_SHOT(n).
+#include "sv_host.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <random>
+
+struct sv_cost_model_s {
+    sv_dtype dt = SV_C128;
+    int n_lo = 0, n_hi = 0;
+    std::vector<double> coef;   // (n - n_lo) * SV_COST_NCLASS + class, seconds
+};
+
+namespace svh {
+namespace {
+
+// Piecewise cubic Hermite interpolation of (x_i = x0 + i, y_i) at x with the
+// Fritsch-Carlson slopes (harmonic mean of neighbouring secants where they
+// agree in sign, zero otherwise; one-sided three-point slopes at the ends,
+// limited to keep the shape): a monotone data set gives a monotone curve.
+double pchip_uniform(const std::vector<double> &y, double x0, double x) {
+    const int m = (int)y.size();
+    if (m == 1) return y[0];
+    const double t = x - x0;
+    int i = (int)std::floor(t);
+    i = std::max(0, std::min(m - 2, i));
+    std::vector<double> d(m - 1);
+    for (int k = 0; k + 1 < m; ++k) d[k] = y[k + 1] - y[k];
+    auto slope = [&](int k) {
+        if (m == 2) return d[0];
+        if (k == 0 || k == m - 1) {
+            const double d0 = k == 0 ? d[0] : d[m - 2], d1 = k == 0 ? d[1] : d[m - 3];
+            double s = (3.0 * d0 - d1) / 2.0;   // three-point end formula, unit spacing
+            if (s * d0 <= 0.0) s = 0.0;
+            else if (d0 * d1 < 0.0 && std::fabs(s) > 3.0 * std::fabs(d0)) s = 3.0 * d0;
+            return s;
+        }
+        const double a = d[k - 1], b = d[k];
+        if (a * b <= 0.0) return 0.0;
+        return 2.0 / (1.0 / a + 1.0 / b);
+    };
+    const double s = t - i, h00 = (2 * s * s * s - 3 * s * s + 1), h10 = (s * s * s - 2 * s * s + s),
+                 h01 = (-2 * s * s * s + 3 * s * s), h11 = (s * s * s - s * s);
+    return h00 * y[i] + h10 * slope(i) + h01 * y[i + 1] + h11 * slope(i + 1);
+}
+
+double coefficient(const sv_cost_model_s &m, int cls, double n) {
+    const int cnt = m.n_hi - m.n_lo + 1;
+    std::vector<double> y(cnt);
+    for (int i = 0; i < cnt; ++i) y[i] = std::log2(m.coef[(size_t)i * SV_COST_NCLASS + cls]);
+    double ly;
+    if (n <= m.n_lo) ly = y[0];                              // below the range: latency floor
+    else if (n >= m.n_hi) ly = y[cnt - 1] + (n - m.n_hi);    // above: 2^n scaling
+    else ly = pchip_uniform(y, m.n_lo, n);
+    return std::exp2(ly);
+}
+
+// Per-gate class of one gate description (by the fraction of amplitudes it changes).
+int gate_class(const GateDesc &d) {
+    if (d.kind == GateDesc::DIAG) return SV_COST_GATE_DIAG;
+    if (d.kind != GateDesc::GROUP) return SV_COST_FUSED_BLOCK;
+    const int lf = __builtin_popcountll(d.group.fm) - d.group.K;   // log2 of 1 / touched fraction
+    return lf <= 0 ? SV_COST_GATE_FULL : lf == 1 ? SV_COST_GATE_HALF : SV_COST_GATE_QUARTER;
+}
+
+// A tiled record touches the whole tile unless it fixes tile bits beyond its
+// flips (a phase pattern, a control on a tile qubit); run terms are part of
+// their run's one sweep.
+int record_class(const svk::TileGate &g) {
+    if (g.kind == 3) return -1;
+    const bool full = g.kind == 2 || (g.kind == 0 ? g.nins == g.K : g.nins == 0);
+    return full ? SV_COST_TILED_RECORD : SV_COST_TILED_RECORD_PART;
+}
+
+double seconds_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+sv_op mk(int kind, int q0, int q1 = 0, double p0 = 0, double p1 = 0, double p2 = 0) {
+    sv_op o;
+    memset(&o, 0, sizeof(o));
+    o.kind = kind;
+    o.q[0] = q0;
+    o.q[1] = q1;
+    o.p[0] = p0;
+    o.p[1] = p1;
+    o.p[2] = p2;
+    return o;
+}
+
+}  // namespace
+
+int choose_mode(sv_ctx c, const sv_op *ops, int nops, int n, int64_t shots) {
+    if (!c || !c->cost) return SV_FUSE_TILED;
+    int best = SV_FUSE_TILED;
+    double tbest = 0.0;
+    bool have = false;
+    for (int mode : {SV_FUSE_TILED, 5, 0}) {
+        double t = 0.0;
+        if (sv_cost_predict(c->cost, ops, nops, n, mode, shots, &t) != SV_OK) continue;
+        if (!have || t < tbest) {
+            best = mode;
+            tbest = t;
+            have = true;
+        }
+    }
+    return best;
+}
+
+}  // namespace svh
+
+using namespace svh;
+
+extern "C" {
+
+sv_status sv_cost_model_create(sv_dtype dt, int n_lo, int n_hi, const double *coef, sv_cost_model *out) {
+    if (!coef || !out || n_lo < 1 || n_hi < n_lo || n_hi > 64) return fail(SV_E_INVALID, "bad argument");
+    if (dt != SV_C64 && dt != SV_C128) return fail(SV_E_INVALID, "dtype must be SV_C64 or SV_C128");
+    const size_t cnt = (size_t)(n_hi - n_lo + 1) * SV_COST_NCLASS;
+    for (size_t i = 0; i < cnt; ++i)
+        if (!(coef[i] > 0.0) || !std::isfinite(coef[i])) return fail(SV_E_INVALID, "coefficients must be finite and > 0");
+    sv_cost_model m = new sv_cost_model_s();
+    m->dt = dt;
+    m->n_lo = n_lo;
+    m->n_hi = n_hi;
+    m->coef.assign(coef, coef + cnt);
+    *out = m;
+    return SV_OK;
+}
+
+sv_status sv_cost_model_table(sv_cost_model m, int *n_lo, int *n_hi, double *coef_out, int capacity) {
+    if (!m) return fail(SV_E_INVALID, "null model");
+    if (n_lo) *n_lo = m->n_lo;
+    if (n_hi) *n_hi = m->n_hi;
+    if (coef_out) {
+        if (capacity < (int)m->coef.size()) return fail(SV_E_INVALID, "capacity too small");
+        std::copy(m->coef.begin(), m->coef.end(), coef_out);
+    }
+    return SV_OK;
+}
+
+sv_status sv_cost_model_destroy(sv_cost_model m) {
+    if (!m) return fail(SV_E_INVALID, "null model");
+    delete m;
+    return SV_OK;
+}
+
+sv_status sv_cost_coefficient(sv_cost_model m, int cls, double n, double *seconds) {
+    if (!m || !seconds || cls < 0 || cls >= SV_COST_NCLASS || !std::isfinite(n)) return fail(SV_E_INVALID, "bad argument");
+    *seconds = coefficient(*m, cls, n);
+    return SV_OK;
+}
+
+sv_status sv_cost_predict(sv_cost_model m, const sv_op *ops, int nops, int n, int fuse_k, int64_t shots,
+                          double *seconds) {
+    if (!m || (!ops && nops) || nops < 0 || shots < 0 || !seconds || n < 1 || n > 64)
+        return fail(SV_E_INVALID, "bad argument");
+    if (fuse_k != 0 && fuse_k != SV_FUSE_TILED && (fuse_k < 2 || fuse_k > SV_MAX_FUSED))
+        return fail(SV_E_INVALID, "fuse_k must be 0, 2..5 or SV_FUSE_TILED");
+    double c[SV_COST_NCLASS];
+    for (int k = 0; k < SV_COST_NCLASS; ++k) c[k] = coefficient(*m, k, n);
+    double t = 0.0;
+    int sweeps = 0;
+    auto op_desc = [&](const sv_op &o, GateDesc &d) {
+        cd U[16];
+        int k, nc;
+        if (!gate_matrix(o.kind, o.p, (o.flags & SV_OP_ADJOINT) != 0, U, &k, &nc)) return false;
+        d = classify(U, k, o.q + nc, o.q, nc);
+        return true;
+    };
+    for (int i = 0; i < nops; ++i) {
+        const int nq = gate_nqubits(ops[i].kind);
+        if (nq < 0) return fail(SV_E_INVALID, "unknown gate kind at op " + std::to_string(i));
+        for (int j = 0; j < nq; ++j)
+            if (ops[i].q[j] < 0 || ops[i].q[j] >= n) return fail(SV_E_INVALID, "op " + std::to_string(i) + " does not fit n");
+    }
+    if (fuse_k == SV_FUSE_TILED) {
+        std::vector<TiledOp> tops;
+        if (!tiled_ops(ops, nops, tops)) return fail(SV_E_INVALID, "unknown gate kind");
+        const int is_c64 = m->dt == SV_C64 ? 1 : 0;
+        const int mbmax = svk::tile_bits(is_c64), lbf = svk::low_bits(is_c64);
+        if (!tops.empty()) {
+            const auto passes = plan_passes(tops, n, mbmax, lbf);
+            std::vector<svk::TileGate> recs;
+            for (const Pass &p : passes) {
+                svk::TileArgs a;
+                pass_records(ops, tops, p, n, mbmax, lbf, recs, a);
+            }
+            t += passes.size() * c[SV_COST_TILED_PASS];
+            for (const svk::TileGate &g : recs)
+                if (record_class(g) >= 0) t += c[record_class(g)];
+            sweeps = (int)passes.size();
+        }
+    } else if (fuse_k == 0 || std::min(fuse_k, n) < 2) {
+        for (int i = 0; i < nops; ++i) {
+            GateDesc d;
+            if (!op_desc(ops[i], d)) return fail(SV_E_INVALID, "unknown gate kind");
+            if (d.kind == GateDesc::NOOP) continue;
+            t += c[gate_class(d)];
+            ++sweeps;
+        }
+    } else {
+        const auto blocks = plan_fusion(ops, nops, std::min(fuse_k, n));
+        for (const Block &b : blocks) {
+            if (b.ops.size() == 1) {
+                GateDesc d;
+                if (!op_desc(ops[b.ops[0]], d)) return fail(SV_E_INVALID, "unknown gate kind");
+                if (d.kind == GateDesc::NOOP) continue;
+                t += c[gate_class(d)];
+            } else {
+                t += b.qubits.size() <= 2 ? c[SV_COST_GATE_FULL] : c[SV_COST_FUSED_BLOCK];
+            }
+            ++sweeps;
+        }
+    }
+    // complex64 renormalisation: a norm read and a scale every 64 sweeps and at the end
+    if (m->dt == SV_C64 && sweeps > 0) t += (sweeps / 64 + 1) * 1.5 * c[SV_COST_GATE_FULL];
+    if (shots > 0) t += c[SV_COST_CDF] + (double)shots * c[SV_COST_SHOT];
+    *seconds = t;
+    return SV_OK;
+}
+
+sv_status sv_ctx_set_cost_model(sv_ctx ctx, sv_cost_model m) {
+    if (!ctx) return fail(SV_E_INVALID, "null context");
+    ctx->cost = m;
+    return SV_OK;
+}
+
+sv_status sv_cost_calibrate(sv_ctx ctx, sv_dtype dt, int n_lo, int n_hi, sv_cost_model *out) {
+    if (!ctx || !out || n_lo < 1 || n_hi < n_lo) return fail(SV_E_INVALID, "bad argument");
+    const int nmax = dt == SV_C64 ? SV_MAX_QUBITS_C64 : SV_MAX_QUBITS_C128;
+    if (dt != SV_C64 && dt != SV_C128) return fail(SV_E_INVALID, "dtype must be SV_C64 or SV_C128");
+    if (n_hi > nmax) return fail(SV_E_INVALID, "n_hi beyond the dtype's limit");
+    const int cnt = n_hi - n_lo + 1;
+    std::vector<double> coef((size_t)cnt * SV_COST_NCLASS, 0.0);
+    std::mt19937_64 rng(12345);
+    std::uniform_real_distribution<double> ang(0.0, 6.283185307179586);
+    for (int n = n_lo; n <= n_hi; ++n) {
+        sv_state st = nullptr;
+        sv_status r = sv_create(ctx, n, dt, &st);
+        if (r) return r;
+        // repetitions: about 32 MiB of state traffic or 16 launches, whichever is more
+        const int R = (int)std::max<double>(16.0, std::min(512.0, std::ldexp(1.0, 25 - n)));
+        auto time_run = [&](const std::vector<sv_op> &ops, int fuse_k) -> double {
+            sv_run(st, ops.data(), (int)ops.size(), fuse_k);   // warm
+            sv_synchronize(st);
+            double best = 1e30;
+            for (int rep = 0; rep < 2; ++rep) {
+                const auto t0 = std::chrono::steady_clock::now();
+                sv_run(st, ops.data(), (int)ops.size(), fuse_k);
+                sv_synchronize(st);
+                best = std::min(best, seconds_since(t0));
+            }
+            return best;
+        };
+        // marginal cost of one item: (time of 3R items - time of R items) / 2R,
+        // which removes the call's fixed host overhead and synchronisation
+        auto marginal = [&](auto make, int fuse_k, double per) -> double {
+            std::vector<sv_op> a1, a3;
+            make(R, a1);
+            make(3 * R, a3);
+            const double t1 = time_run(a1, fuse_k), t3 = time_run(a3, fuse_k);
+            return std::max(1e-9, (t3 - t1) / (2.0 * R * per));
+        };
+        double *row = &coef[(size_t)(n - n_lo) * SV_COST_NCLASS];
+        std::uniform_int_distribution<int> qd(0, n - 1);
+        auto two = [&](int &a, int &b) {
+            a = qd(rng);
+            do b = qd(rng); while (b == a);
+        };
+        // per-gate classes: gates on uniformly random qubits
+        row[SV_COST_GATE_FULL] = marginal([&](int cnt, std::vector<sv_op> &o) {
+            for (int i = 0; i < cnt; ++i) o.push_back(mk(SV_GATE_U3, qd(rng), 0, ang(rng), ang(rng), ang(rng)));
+        }, 0, 1.0);
+        if (n >= 2) {
+            auto pairs = [&](int kind, bool angle) {
+                return [&, kind, angle](int cnt, std::vector<sv_op> &o) {
+                    for (int i = 0; i < cnt; ++i) {
+                        int a, b;
+                        two(a, b);
+                        o.push_back(mk(kind, a, b, angle ? ang(rng) : 0.0));
+                    }
+                };
+            };
+            row[SV_COST_GATE_HALF] = marginal(pairs(SV_GATE_CX, false), 0, 1.0);
+            row[SV_COST_GATE_QUARTER] = marginal(pairs(SV_GATE_CP, true), 0, 1.0);
+            row[SV_COST_GATE_DIAG] = marginal(pairs(SV_GATE_RZZ, true), 0, 1.0);
+        } else {
+            row[SV_COST_GATE_HALF] = row[SV_COST_GATE_QUARTER] = row[SV_COST_GATE_DIAG] = row[SV_COST_GATE_FULL];
+        }
+        // fused blocks: dense min(5, n)-qubit blocks on random target sets
+        if (n >= 3) {
+            const int k = std::min(5, n), K = 1 << k;
+            std::vector<double> U(2 * K * K, 0.0);
+            for (int r = 0; r < K; ++r) U[2 * (r * K + (r * 7 + 3) % K)] = 1.0;   // a permutation: unitary
+            auto apply_blocks = [&](int cnt) {
+                for (int i = 0; i < cnt; ++i) {
+                    int tg[5], m = 0;
+                    while (m < k) {
+                        const int q = qd(rng);
+                        bool dup = false;
+                        for (int j = 0; j < m; ++j) dup = dup || tg[j] == q;
+                        if (!dup) tg[m++] = q;
+                    }
+                    sv_apply_fused(st, U.data(), k, tg);
+                }
+            };
+            apply_blocks(2);
+            sv_synchronize(st);
+            auto t0 = std::chrono::steady_clock::now();
+            apply_blocks(R);
+            sv_synchronize(st);
+            const double t1 = seconds_since(t0);
+            t0 = std::chrono::steady_clock::now();
+            apply_blocks(3 * R);
+            sv_synchronize(st);
+            const double t3 = seconds_since(t0);
+            row[SV_COST_FUSED_BLOCK] = std::max(1e-9, (t3 - t1) / (2.0 * R));
+        } else {
+            row[SV_COST_FUSED_BLOCK] = row[SV_COST_GATE_FULL];
+        }
+        // fixed cost of one sv_run call (host validation, launch, synchronisation)
+        std::vector<sv_op> one{mk(SV_GATE_U3, 0, 0, 0.3, 0.2, 0.1)};
+        const double call = std::max(0.0, time_run(one, 0) - row[SV_COST_GATE_FULL]);
+        // tiled passes: records by difference inside one pass (on <= 12 qubits,
+        // which always fit one tile), then the pass itself
+        {
+            const int is_c64 = dt == SV_C64 ? 1 : 0;
+            const int tq = std::min(n, 12);
+            std::uniform_int_distribution<int> td(0, tq - 1);
+            auto nrec = [&](const std::vector<sv_op> &o, int cls) {
+                std::vector<TiledOp> tops;
+                tiled_ops(o.data(), (int)o.size(), tops);
+                const auto passes = plan_passes(tops, n, svk::tile_bits(is_c64), svk::low_bits(is_c64));
+                std::vector<svk::TileGate> recs;
+                for (const Pass &p : passes) {
+                    svk::TileArgs a;
+                    pass_records(o.data(), tops, p, n, svk::tile_bits(is_c64), svk::low_bits(is_c64), recs, a);
+                }
+                double c = 0;
+                for (const svk::TileGate &g : recs) c += record_class(g) == cls;
+                return c;
+            };
+            auto per_record = [&](auto make, int cls) {
+                std::vector<sv_op> a1, a3;
+                make(3 * R, a1);
+                make(9 * R, a3);
+                const double r1 = nrec(a1, cls), r3 = nrec(a3, cls);
+                const double t1 = time_run(a1, SV_FUSE_TILED), t3 = time_run(a3, SV_FUSE_TILED);
+                return std::max(1e-9, (t3 - t1) / std::max(1.0, r3 - r1));
+            };
+            // whole-tile records: 2-qubit blocks (U3, U3, CX on neighbours)
+            row[SV_COST_TILED_RECORD] = per_record([&](int cnt, std::vector<sv_op> &o) {
+                for (int l = 0; (int)o.size() < cnt; ++l)
+                    for (int q = l & 1; q + 1 < tq && (int)o.size() < cnt; q += 2) {
+                        o.push_back(mk(SV_GATE_U3, q, 0, ang(rng), ang(rng), ang(rng)));
+                        o.push_back(mk(SV_GATE_U3, q + 1, 0, ang(rng), ang(rng), ang(rng)));
+                        o.push_back(mk(SV_GATE_CX, q, q + 1));
+                    }
+            }, SV_COST_TILED_RECORD);
+            // part-tile records: controlled phases on random tile qubits
+            if (tq >= 2)
+                row[SV_COST_TILED_RECORD_PART] = per_record([&](int cnt, std::vector<sv_op> &o) {
+                    for (int i = 0; i < cnt; ++i) {
+                        int a = td(rng), b;
+                        do b = td(rng); while (b == a);
+                        o.push_back(mk(SV_GATE_CP, a, b, ang(rng)));
+                    }
+                }, SV_COST_TILED_RECORD_PART);
+            else
+                row[SV_COST_TILED_RECORD_PART] = row[SV_COST_TILED_RECORD];
+            row[SV_COST_TILED_PASS] = std::max(1e-9, time_run(one, SV_FUSE_TILED) - call - row[SV_COST_TILED_RECORD]);
+        }
+        // shots: sampling 1 shot (the CDF pass) and many shots
+        {
+            std::vector<uint64_t> buf(65536);
+            sv_sample(st, 1, 1, buf.data());
+            auto t0 = std::chrono::steady_clock::now();
+            for (int i = 0; i < 4; ++i) sv_sample(st, 1, 2 + i, buf.data());
+            const double t1 = seconds_since(t0) / 4;
+            t0 = std::chrono::steady_clock::now();
+            sv_sample(st, 65536, 9, buf.data());
+            const double tS = seconds_since(t0);
+            row[SV_COST_CDF] = std::max(1e-9, t1);
+            row[SV_COST_SHOT] = std::max(1e-12, (tS - t1) / 65535.0);
+        }
+        sv_destroy(st);
+        for (int k = 0; k < SV_COST_NCLASS; ++k)
+            if (!(row[k] > 0.0)) row[k] = 1e-9;
+    }
+    return sv_cost_model_create(dt, n_lo, n_hi, coef.data(), out);
+}
+
+}  // extern "C"

@@ -534,6 +534,17 @@ bool advance_large(sv_server s) {
     for (Req *r : s->large) {
         if (r->measuring) continue;
         const int R = r->st->is_c64() ? s->ctx->renorm_period : 0;
+        if (!r->prepared && r->fuse_k == SV_FUSE_AUTO) {
+            // the mode the cost model predicts fastest, chosen outside the server lock
+            r->fuse_k = choose_mode(s->ctx, r->ops.data(), (int)r->ops.size(), r->n, r->shots);
+            if (r->fuse_k >= 2) {
+                r->blocks = plan_fusion(r->ops.data(), (int)r->ops.size(), std::min(r->fuse_k, r->n));
+                r->total = r->blocks.size();
+            } else if (r->fuse_k == 0) {
+                r->total = r->ops.size();
+                r->prepared = true;
+            }
+        }
         if (!r->prepared && !(r->fuse_k == SV_FUSE_TILED ? prepare_passes(s, r) : prepare_blocks(s, r))) continue;
         int budget = kChunk;
         sv_status q = SV_OK;
@@ -653,8 +664,9 @@ sv_status validate(sv_server s, const sv_circuit *c) {
     if (c->nops < 0 || (c->nops > 0 && !c->ops)) return fail(SV_E_INVALID, "bad op list");
     if (c->nterms < 0 || (c->nterms > 0 && !c->terms)) return fail(SV_E_INVALID, "bad term list");
     if (c->shots < 0 || c->shots > kMaxShots) return fail(SV_E_INVALID, "shots out of range [0, 2^24]");
-    if (c->fuse_k != 0 && c->fuse_k != SV_FUSE_TILED && (c->fuse_k < 2 || c->fuse_k > SV_MAX_FUSED))
-        return fail(SV_E_INVALID, "fuse_k must be 0, 2..5 or SV_FUSE_TILED");
+    if (c->fuse_k != 0 && c->fuse_k != SV_FUSE_TILED && c->fuse_k != SV_FUSE_AUTO &&
+        (c->fuse_k < 2 || c->fuse_k > SV_MAX_FUSED))
+        return fail(SV_E_INVALID, "fuse_k must be 0, 2..5, SV_FUSE_TILED or SV_FUSE_AUTO");
     for (int i = 0; i < c->nops; ++i) {
         const sv_op &o = c->ops[i];
         const int nq = gate_nqubits(o.kind);

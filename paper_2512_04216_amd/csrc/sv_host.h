@@ -125,6 +125,7 @@ struct sv_ctx_s {
     svh::Tracer tracer;
     svh::ParamRing ring;
     svh::StagePool stage;
+    sv_cost_model cost = nullptr;   // borrowed, for SV_FUSE_AUTO
     int nstates = 0;
     std::mutex mu;
 };
@@ -168,6 +169,11 @@ sv_status apply_matrix(sv_state st, const cd *U, int k, const int *targets, cons
 sv_status apply_fused(sv_state st, const cd *U, int k, const int *targets);
 // whether a k-qubit block on n qubits runs on the MFMA kernel (SV_NO_MFMA set: never)
 bool fused_use_mfma(int n, int k);
+
+// SV_FUSE_AUTO: the mode (0, 5, SV_FUSE_TILED) the context's cost model
+// predicts fastest for these ops on n qubits with `shots` shots; SV_FUSE_TILED
+// without a model.
+int choose_mode(sv_ctx c, const sv_op *ops, int nops, int n, int64_t shots);
 
 // fusion planning
 struct Block {

@@ -1,0 +1,96 @@
+"""Cost model (Sec. III-C, Eq. (1)) on the host: the coefficient curves are
+piecewise cubic Hermite interpolants of log2 C over n (checked against scipy's
+PchipInterpolator, an independent implementation of the same Fritsch-Carlson
+construction), scale as 2^n beyond the calibrated range, and a prediction is
+the plain sum of the coefficients of the operations a run launches."""
+import math
+
+import numpy as np
+import pytest
+import scipy.interpolate
+
+import workloads as W
+
+NCLS = 10
+
+
+def _S():
+    import paper_2512_04216_amd as S
+
+    S.load()
+    return S
+
+
+def test_coefficients_are_pchip_of_log2():
+    S = _S()
+    rng = np.random.default_rng(3)
+    lo, hi = 6, 20
+    ns = np.arange(lo, hi + 1)
+    # increasing-ish curves with a flat start (launch latency) and noise
+    tab = np.zeros((ns.size, NCLS))
+    for c in range(NCLS):
+        base = np.maximum(ns - rng.integers(8, 14), 0) * rng.uniform(0.8, 1.1)
+        tab[:, c] = np.exp2(-18 + base + rng.normal(0, 0.15, ns.size) + c * 0.1)
+    m = S.CostModel.from_table("c128", lo, hi, tab)
+    for c in range(NCLS):
+        ref = scipy.interpolate.PchipInterpolator(ns, np.log2(tab[:, c]))
+        for x in np.linspace(lo, hi, 57):
+            got = m.coefficient(c, x)
+            assert abs(math.log2(got) - float(ref(x))) <= 1e-12
+        for i, n in enumerate(ns):                        # data points reproduced
+            assert m.coefficient(c, float(n)) == pytest.approx(tab[i, c], rel=1e-14)
+        # beyond the range: 2^n scaling above, the first value below
+        assert m.coefficient(c, hi + 3) == pytest.approx(tab[-1, c] * 8, rel=1e-12)
+        assert m.coefficient(c, lo - 2) == pytest.approx(tab[0, c], rel=1e-14)
+    lo2, hi2, back = m.table()
+    assert (lo2, hi2) == (lo, hi) and np.array_equal(back, tab)
+
+
+def test_monotone_data_gives_monotone_curve():
+    S = _S()
+    lo, hi = 4, 16
+    y = np.cumsum(np.abs(np.random.default_rng(5).normal(0, 1, hi - lo + 1)) ** 3)   # steps of mixed size
+    tab = np.tile(np.exp2(y - y.max())[:, None], (1, NCLS))
+    m = S.CostModel.from_table("c64", lo, hi, tab)
+    xs = np.linspace(lo, hi, 400)
+    v = np.array([m.coefficient(0, x) for x in xs])
+    assert np.all(np.diff(v) >= -1e-15 * v[1:])
+
+
+def test_prediction_is_the_sum_of_operation_costs():
+    # distinct powers of two per class make every term visible in the sum
+    S = _S()
+    lo, hi = 2, 12
+    row = np.array([2.0 ** c for c in range(NCLS)])   # full, half, quarter, diag, fused, pass, record, cdf, shot, part
+    m = S.CostModel.from_table("c128", lo, hi, np.tile(row, (hi - lo + 1, 1)))
+    ops = [("u3", (0,), (0.1, 0.2, 0.3)), ("h", (3,), ()), ("cx", (0, 1), ()), ("s", (2,), ()),
+           ("cp", (1, 2), (0.4,)), ("ccx", (0, 1, 2), ()), ("rz", (2,), (0.5,)), ("rzz", (0, 3), (0.6,)),
+           ("z", (1,), ()), ("x", (4,), ())]
+    # full: u3 h x -> 3; half: cx s z -> 3; quarter: cp ccx -> 2; diag: rz rzz -> 2
+    want = 3 * 1 + 3 * 2 + 2 * 4 + 2 * 8
+    assert m.predict(ops, 6, 0, 0) == want
+    assert m.predict(ops, 6, 0, 5) == want + 128 + 5 * 256
+    # the identity costs nothing; per-gate cost does not depend on n here (flat table)
+    assert m.predict([("rz", (0,), (0.0,))] * 3, 6, 0, 0) == 0.0
+    # tiled: one pass (6 qubits fit a tile); its records are the ops after in-pass
+    # fusion, whole-tile ones at 64 and part-tile ones at 512
+    t = m.predict(ops, 6, -1, 0)
+    assert t >= 32 + 64 and (t - 32) % 64 == 0
+    # complex64 adds the renormalisation at the end of the run (1.5 full sweeps)
+    m64 = S.CostModel.from_table("c64", lo, hi, np.tile(row, (hi - lo + 1, 1)))
+    assert m64.predict(ops, 6, 0, 0) == want + 1.5
+
+
+def test_invalid_cost_model_arguments():
+    S = _S()
+    with pytest.raises(S.SvError):
+        S.CostModel.from_table("c128", 5, 4, np.ones(NCLS))
+    with pytest.raises(S.SvError):
+        S.CostModel.from_table("c128", 4, 4, -np.ones(NCLS))
+    m = S.CostModel.from_table("c128", 4, 6, np.ones((3, NCLS)))
+    with pytest.raises(S.SvError):
+        m.predict([("cx", (0, 7), ())], 6, 0, 0)          # qubit beyond n
+    with pytest.raises(S.SvError):
+        m.predict([("h", (0,), ())], 6, 7, 0)             # fuse_k out of range
+    with pytest.raises(S.SvError):
+        m.coefficient(NCLS, 5)
