@@ -333,6 +333,45 @@ def bench_small(S, reps=200, batch=2000):
     return out
 
 
+def bench_cost(S, dtype="c128", n_lo=8, n_hi=28):
+    """Cost model (runtime prediction by calibrated operation costs): the
+    calibration time, then predicted vs measured seconds of four circuits in
+    each run mode (one kernel per gate, fused blocks, tiled passes), and the
+    mode SV_FUSE_AUTO would take."""
+    import torch
+
+    import workloads as W
+
+    ctx = S.Context(arena_bytes=40 << 30)
+    t0 = time.perf_counter()
+    m = S.CostModel.calibrate(ctx, dtype, n_lo, n_hi)
+    out = {"dtype": dtype, "n_range": [n_lo, n_hi], "calibration_s": round(time.perf_counter() - t0, 2)}
+    cases = [("brickwork_28q_20l", 28, W.brickwork(28, 20, seed=SEED)), ("qft_28q", 28, W.qft(28)),
+             ("random_24q_800g", 24, W.random_circuit(24, 800, seed=3)),
+             ("brickwork_16q_20l", 16, W.brickwork(16, 20, seed=1))]
+    names = {0: "per_gate", 5: "fused", S.SV_FUSE_TILED: "tiled"}
+    for name, n, ops in cases:
+        arr = S.ops_to_numpy(ops)
+        st = S.State(ctx, n, dtype)
+        res = {}
+        for fk in (0, 5, S.SV_FUSE_TILED):
+            st.run(arr, fuse_k=fk)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            st.run(arr, fuse_k=fk)
+            torch.cuda.synchronize()
+            res[names[fk]] = {"predicted_ms": round(m.predict(ops, n, fk, 0) * 1e3, 2),
+                              "measured_ms": round((time.perf_counter() - t) * 1e3, 2)}
+        st.close()
+        res["auto_picks"] = min(res, key=lambda k: res[k]["predicted_ms"])
+        res["fastest"] = min(res, key=lambda k: res[k]["measured_ms"] if isinstance(res[k], dict) else 1e30)
+        out[name] = res
+        print("bench cost: %s %s" % (name, res), file=sys.stderr, flush=True)
+    m.close()
+    ctx.close()
+    return out
+
+
 def bench_serving(S, count=10000, baseline_count=300, loads=(0.5, 0.8, 0.95)):
     """Serving stream: `count` circuits, n uniform 8..26, depth uniform 5..40,
     gates uniform from {H,S,T,RX,RY,RZ,CNOT,CZ,SWAP}, 1000 shots, complex64.
@@ -418,7 +457,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c64", action="store_true", help="skip the complex64 side measurement")
     ap.add_argument("--no-trace", action="store_true")
-    ap.add_argument("--config", default="28q", choices=["28q", "small", "fused", "qaoa", "serving"],
+    ap.add_argument("--config", default="28q", choices=["28q", "small", "fused", "qaoa", "serving", "cost"],
                     help="28q (default): the headline line; the others print their own JSON line")
     ap.add_argument("--serving-count", type=int, default=10000)
     args = ap.parse_args()
@@ -435,7 +474,7 @@ def main():
     if args.config != "28q":
         fn = {"fused": lambda: bench_fused(S), "qaoa": lambda: bench_qaoa(S),
               "serving": lambda: bench_serving(S, count=args.serving_count),
-              "small": lambda: bench_small(S)}[args.config]
+              "small": lambda: bench_small(S), "cost": lambda: bench_cost(S)}[args.config]
         print(json.dumps({"config": args.config, "result": fn()}))
         return
     print("bench: 28-qubit brickwork + QFT, %s, %d warmup + %d timed steps" % (args.dtype, args.warmup, args.steps),
