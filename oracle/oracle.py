@@ -198,34 +198,53 @@ def collapse(psi: np.ndarray, q: int, m: int, pm: float, reset: bool = False):
     return psi
 
 
+def cond_met(op, clbits: int) -> bool:
+    """A gate (name, qubits, params, adjoint, (clbit, value)) runs only when
+    classical bit `clbit` holds `value`; gates without a fifth entry always run."""
+    if len(op) < 5 or op[4] is None:
+        return True
+    c, v = op[4]
+    return ((int(clbits) >> int(c)) & 1) == (1 if v else 0)
+
+
+def trajectory(ops, n: int, seed: int, shot: int = 0, start: np.ndarray | None = None):
+    """One shot of a circuit with mid-circuit measurements, resets and
+    classically conditioned gates (Sec. III-B, Sec. III-E). At the k-th
+    measure/reset (k = 0..K-1 in list order) the shot draws
+    u = U01(seed, shot*(K+1) + k); the qubit reads 1 exactly when
+    u*(p0+p1) >= p0, and the state is projected and rescaled. Returns
+    (clbits, final state, K)."""
+    K = sum(1 for o in ops if o[0] in ("measure", "reset"))
+    st = basis_state(n, 0) if start is None else start.copy()
+    clbits = 0
+    k = 0
+    for op in ops:
+        if op[0] in ("measure", "reset"):
+            q = int(op[1][0])
+            p0, p1 = qubit_probs(st, q)
+            u = u01(seed, shot * (K + 1) + k)
+            m = 1 if u * (p0 + p1) >= p0 else 0
+            collapse(st, q, m, p1 if m else p0, reset=(op[0] == "reset"))
+            if op[0] == "measure":
+                b = 1 << int(op[1][1])
+                clbits = (clbits | b) if m else (clbits & ~b)
+            k += 1
+        elif cond_met(op, clbits):
+            apply_op(st, op[:3], adjoint=bool(len(op) > 3 and op[3]))
+    return clbits, st, K
+
+
 def run_shots(ops, n: int, shots: int, seed: int, basis: int = 0, psi: np.ndarray | None = None):
     """Every shot simulated on its own from the start (Sec. III-B: with
-    mid-circuit measurements or resets each shot is its own trajectory).
-    ops may hold ("measure", (qubit, clbit), ()) and ("reset", (qubit,), ()).
-    At the k-th measure/reset (k = 0..K-1 in list order) shot s draws
-    u = U01(seed, s*(K+1) + k), the qubit reads 1 exactly when u*(p0+p1) >= p0,
-    and the state is projected and rescaled; the terminal sample of all qubits
-    uses counter s*(K+1) + K. Returns (clbits, samples), one entry per shot."""
-    K = sum(1 for o in ops if o[0] in ("measure", "reset"))
+    mid-circuit measurements or resets each shot is its own trajectory, see
+    trajectory()); the terminal sample of all qubits uses counter
+    s*(K+1) + K. Returns (clbits, samples), one entry per shot."""
     start = basis_state(n, basis) if psi is None else psi
     clbits = np.zeros(shots, dtype=np.uint64)
     samples = np.zeros(shots, dtype=np.uint64)
     for s in range(shots):
-        st = start.copy()
-        k = 0
-        for op in ops:
-            if op[0] in ("measure", "reset"):
-                q = int(op[1][0])
-                p0, p1 = qubit_probs(st, q)
-                u = u01(seed, s * (K + 1) + k)
-                m = 1 if u * (p0 + p1) >= p0 else 0
-                collapse(st, q, m, p1 if m else p0, reset=(op[0] == "reset"))
-                if op[0] == "measure":
-                    b = np.uint64(1) << np.uint64(op[1][1])
-                    clbits[s] = (clbits[s] | b) if m else (clbits[s] & ~b)
-                k += 1
-            else:
-                apply_op(st, op)
+        cl, st, K = trajectory(ops, n, seed, shot=s, start=start)
+        clbits[s] = np.uint64(cl)
         samples[s] = sample_at(st, [s * (K + 1) + K], seed)[0]
     return clbits, samples
 

@@ -23,4 +23,7 @@ from .circuits import (  # noqa: F401
     random_state,
     random_unitary,
     random_paulis,
+    c_if,
+    remote_cx,
+    dqc,
 )

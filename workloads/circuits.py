@@ -220,3 +220,49 @@ def random_paulis(n: int, count: int, seed: int):
         z = int(rng.integers(0, 1 << n))
         out.append((x, z, float(rng.uniform(-1, 1))))
     return out
+
+
+def c_if(op, clbit: int, value: int):
+    """The gate `op` applied only when classical bit `clbit` holds `value`."""
+    return (op[0], op[1], op[2], False, (int(clbit), int(value)))
+
+
+def remote_cx(a: int, b: int, ca: int, cb: int, m1: int, m2: int):
+    """CNOT from qubit a (one host) to qubit b (another host) through the
+    communication qubits ca (on a's host) and cb (on b's host), both |0> on
+    entry: an entangled pair on (ca, cb); the cat-entangler (CX a->ca, measure
+    ca into classical bit m1, X on cb if it read 1); CX cb->b; the disentangler
+    (H on cb, measure cb into m2, Z on a if it read 1); then both communication
+    qubits reset to |0>."""
+    return [_op("h", (ca,)), _op("cx", (ca, cb)), _op("cx", (a, ca)), ("measure", (ca, m1), ()),
+            c_if(_op("x", (cb,)), m1, 1), _op("cx", (cb, b)), _op("h", (cb,)), ("measure", (cb, m2), ()),
+            c_if(_op("z", (a,)), m2, 1), ("reset", (ca,), ()), ("reset", (cb,), ())]
+
+
+def dqc(hosts: int, m: int, rounds: int, links, seed: int):
+    """A distributed circuit (Sec. III-E): `hosts` hosts of m computational
+    qubits (host h holds qubits h*m .. h*m+m-1) and two communication qubits per
+    link (link l, between hosts links[l] = (h1, h2), owns qubits hosts*m + 2l
+    and hosts*m + 2l + 1). Each round applies one brickwork layer inside every
+    host (U3 on each qubit, angles iid uniform [0, 2*pi) drawn qubit by qubit
+    as theta, phi, lambda, then CNOTs on neighbour pairs starting at offset
+    round % 2) and then, for every link, a remote CNOT from qubit r % m of h1 to
+    qubit (3r + 1) % m of h2 (r = round index) through the link's
+    communication qubits, its two measurements into classical bits 2l % 64 and
+    (2l + 1) % 64. Returns (ops, total qubits)."""
+    rng = np.random.default_rng(seed)
+    links = [tuple(x) for x in links]
+    n = hosts * m + 2 * len(links)
+    ops = []
+    for r in range(rounds):
+        for h in range(hosts):
+            base = h * m
+            ang = rng.uniform(0.0, TWO_PI, size=(m, 3))
+            for q in range(m):
+                ops.append(_op("u3", (base + q,), ang[q]))
+            for c in range(r % 2, m - 1, 2):
+                ops.append(_op("cx", (base + c, base + c + 1)))
+        for l, (h1, h2) in enumerate(links):
+            ca, cb = hosts * m + 2 * l, hosts * m + 2 * l + 1
+            ops += remote_cx(h1 * m + r % m, h2 * m + (3 * r + 1) % m, ca, cb, (2 * l) % 64, (2 * l + 1) % 64)
+    return ops, n
