@@ -278,6 +278,72 @@ def bench_qaoa(S):
     return out
 
 
+def bench_pblock(S, m=15, rounds=8):
+    """p-block states on distributed circuits (hosts of m qubits linked by remote
+    CNOTs through communication qubits, see workloads.dqc): 2 hosts against the
+    monolithic state of all 2m+2 qubits (sv_run_shots, one shot, same draws),
+    then 7 hosts (three linked pairs and one alone) whose 7m+6 qubits no single
+    state could hold. complex128, tiled passes inside blocks."""
+    import torch
+
+    import workloads as W
+
+    out = {}
+    ops, n = W.dqc(2, m, rounds, [(0, 1)], seed=SEED + 7)
+    seed = SEED + 8
+    # block states of different sizes come and go in a first-fit arena: the
+    # arena needs room beyond the live peak (1.5x the monolithic state)
+    ctx = S.Context(arena_bytes=(32 << (2 * m + 2)) + (32 << 30))
+    with S.PBlock(ctx, n, "c128") as pb:
+        ctx.trace_read()
+        ctx.trace(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cl = pb.run(ops, seed=seed, fuse_k=S.SV_FUSE_TILED)
+        t_pb = time.perf_counter() - t0
+        ctx.trace(False)
+        tr = ctx.trace_read()
+        nb, big, by, peak = pb.info()
+    kern = {k: {"launches": v["launches"], "avg_us": round(1e6 * v["seconds"] / max(1, v["launches"]), 1),
+                "GBps": round(v["bytes"] / max(v["seconds"], 1e-12) / 1e9, 1)}
+            for k, v in tr.items() if k in ("kron", "split", "tiled_pass")}
+    print("bench: p-block 2 hosts done in %.3f s" % t_pb, file=sys.stderr, flush=True)
+    with S.State(ctx, n, "c128") as st:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cls, _ = st.run_shots(ops, 1, seed, fuse_k=S.SV_FUSE_TILED, samples=False)
+        torch.cuda.synchronize()
+        t_mono = time.perf_counter() - t0
+    print("bench: monolithic %d qubits done in %.3f s" % (n, t_mono), file=sys.stderr, flush=True)
+    ctx.close()
+    torch.cuda.empty_cache()
+    out["two_hosts"] = {"qubits": n, "host_qubits": m, "rounds": rounds, "ops": len(ops),
+                        "pblock_s": round(t_pb, 3), "monolithic_s": round(t_mono, 3),
+                        "speedup": round(t_mono / t_pb, 2), "clbits_equal": int(cls[0]) == cl,
+                        "pblock_final_bytes": by, "pblock_peak_bytes": peak, "largest_block": big,
+                        "monolithic_bytes": 16 << n, "kernels": kern}
+    hosts, links = 7, [(0, 1), (2, 3), (4, 5)]
+    ops, n = W.dqc(hosts, m, rounds, links, seed=SEED + 9)
+    ctx = S.Context(arena_bytes=(32 << (2 * m + 2)) + len(links) * (16 << (2 * m)) + (4 << 30))
+    with S.PBlock(ctx, n, "c128") as pb:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pb.run(ops, seed=seed, fuse_k=S.SV_FUSE_TILED)
+        t_pb = time.perf_counter() - t0
+        nb, big, by, peak = pb.info()
+        vals, _ = pb.expect([(0, 1 << q, 1.0) for q in (0, m, 2 * m, 6 * m)])
+        t0 = time.perf_counter()
+        smp = pb.sample(100000, seed + 1)
+        t_s = time.perf_counter() - t0
+    ctx.close()
+    print("bench: p-block %d qubits done in %.3f s" % (n, t_pb), file=sys.stderr, flush=True)
+    out["seven_hosts"] = {"qubits": n, "host_qubits": m, "links": links, "rounds": rounds, "ops": len(ops),
+                          "pblock_s": round(t_pb, 3), "blocks": nb, "largest_block": big, "final_bytes": by,
+                          "peak_bytes": peak, "z_expect": [round(v, 6) for v in vals],
+                          "sample_100k_s": round(t_s, 3), "sample_words": int(smp.shape[1])}
+    return out
+
+
 def bench_small(S, reps=200, batch=2000):
     """12-qubit brickwork, 20 layers (350 gates), complex128, 1024 shots: a
     latency-bound circuit (the whole state is 64 KiB). Microseconds per
@@ -457,7 +523,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c64", action="store_true", help="skip the complex64 side measurement")
     ap.add_argument("--no-trace", action="store_true")
-    ap.add_argument("--config", default="28q", choices=["28q", "small", "fused", "qaoa", "serving", "cost"],
+    ap.add_argument("--config", default="28q", choices=["28q", "small", "fused", "qaoa", "serving", "cost", "pblock"],
                     help="28q (default): the headline line; the others print their own JSON line")
     ap.add_argument("--serving-count", type=int, default=10000)
     args = ap.parse_args()
@@ -474,7 +540,8 @@ def main():
     if args.config != "28q":
         fn = {"fused": lambda: bench_fused(S), "qaoa": lambda: bench_qaoa(S),
               "serving": lambda: bench_serving(S, count=args.serving_count),
-              "small": lambda: bench_small(S), "cost": lambda: bench_cost(S)}[args.config]
+              "small": lambda: bench_small(S), "cost": lambda: bench_cost(S),
+              "pblock": lambda: bench_pblock(S)}[args.config]
         print(json.dumps({"config": args.config, "result": fn()}))
         return
     print("bench: 28-qubit brickwork + QFT, %s, %d warmup + %d timed steps" % (args.dtype, args.warmup, args.steps),

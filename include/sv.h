@@ -151,9 +151,16 @@ typedef struct {
     int32_t kind;     /* sv_gate_kind */
     int32_t flags;    /* SV_OP_ADJOINT or 0 */
     int32_t q[3];     /* qubits, controls first */
-    int32_t pad;
+    int32_t cond;     /* 0, or SV_OP_COND(c, v): classically conditioned gate */
     double p[3];      /* angles: RX RY RZ P CP RZZ use p[0]; U3 uses theta, phi, lambda */
 } sv_op;
+
+/* sv_op.cond of a gate applied only when classical bit c (0..63) holds v (0 or
+ * 1): the correction steps of dynamic circuits (Sec. III-E, mid-circuit
+ * measurements that steer later gates). Accepted by sv_run_shots and
+ * sv_pblock_run, which know each trajectory's classical bits; sv_run and
+ * sv_submit reject a nonzero cond. */
+#define SV_OP_COND(c, v) (1 + (c) + 64 * ((v) != 0))
 
 /* The 2^k x 2^k matrix of a gate kind on its target qubits and its number of
  * controls (host only, no state needed). U_out holds 16 complex128 values. */
@@ -208,8 +215,10 @@ sv_status sv_plan_passes(const sv_op *ops, int nops, int n, sv_dtype dt, int *np
  * fuse_k. Outputs (caller-owned, `shots` entries each): clbits_out[s] holds the
  * shot's classical bits (bit c = outcome of the last SV_OP_MEASURE into c, 0 if
  * none); samples_out (nullable) the shot's terminal measurement of all qubits,
- * the inverse-CDF draw of sv_sample with counter s*(K+1) + K. st afterwards
- * holds the final state of one of the branches. Synchronous. */
+ * the inverse-CDF draw of sv_sample with counter s*(K+1) + K. A gate with a
+ * nonzero cond (SV_OP_COND) runs in the branches whose classical bits meet it
+ * and is skipped in the others. st afterwards holds the final state of one of
+ * the branches. Synchronous. */
 sv_status sv_run_shots(sv_state st, const sv_op *ops, int nops, int fuse_k, int64_t shots, uint64_t seed,
                        uint64_t *clbits_out, uint64_t *samples_out);
 
@@ -245,6 +254,79 @@ typedef struct {
  * share one pass over the state; each other term takes one pass. */
 sv_status sv_expect(sv_state st, const sv_pauli *terms, int nterms, double *out_each,
                     double *out_weighted);
+
+/* ----------------------------------------------------- p-block states */
+
+/* A partitioned-block (p-block) state of n qubits (Sec. II, p-block
+ * simulation; Sec. III-E, distributed circuits): the state is held as a tensor
+ * product of blocks, each an ordinary device state of the qubits it holds.
+ * Every qubit starts in a block of its own; a gate on qubits of several
+ * blocks first merges them into their tensor product; a measured or reset
+ * qubit leaves its block (the projected state factors into the qubit's basis
+ * state and the rest), so memory follows the entanglement actually created
+ * rather than n. Qubit q's amplitude index bits are global: with W = (n + 63)
+ * / 64 words per index, qubit q is bit q % 64 of word q / 64. */
+typedef struct sv_pblock_s *sv_pblock;
+
+#define SV_PBLOCK_MAX_QUBITS 1024
+
+/* n qubits (1..SV_PBLOCK_MAX_QUBITS) of type dt, all |0>, in n blocks; every
+ * block state lives in c's arena (SV_E_OOM when one does not fit). */
+sv_status sv_pblock_create(sv_ctx c, int n, sv_dtype dt, sv_pblock *out);
+sv_status sv_pblock_destroy(sv_pblock p);
+
+/* Run ops in list order. Gates on one block queue up on it and run as sv_run
+ * with fuse_k on the block's state when the block next merges, is measured
+ * or is read, or when the call ends. A gate whose qubits lie in several blocks
+ * merges them first (smaller block in the low index bits; the largest merged
+ * block must fit SV_MAX_QUBITS_* and the arena). SV_OP_MEASURE / SV_OP_RESET:
+ * the k-th of the call (k = 0..K-1) draws u = U01(seed, k) and reads 1
+ * exactly when u*(p0+p1) >= p0, with FP64 p0, p1 of the qubit in its block
+ * (the trajectory of shot 0 of sv_run_shots with the same seed); the block
+ * is projected and rescaled by 1/sqrt(p_m), and when it holds other qubits
+ * the qubit leaves it in the basis state |m> (|0> after a reset) while the
+ * rest keeps the projected amplitudes. *clbits (in/out, one word) holds the
+ * classical bits: SV_OP_COND gates test it, SV_OP_MEASURE writes it.
+ * Synchronous. */
+sv_status sv_pblock_run(sv_pblock p, const sv_op *ops, int nops, int fuse_k, uint64_t seed,
+                        uint64_t *clbits);
+
+/* Blocks, the largest block's qubit count, the bytes of all block states and
+ * the most bytes they held at once since creation, counting both sides of a
+ * merge or split (any output may be NULL). */
+sv_status sv_pblock_info(sv_pblock p, int *nblocks, int *largest, uint64_t *state_bytes,
+                         uint64_t *peak_bytes);
+
+/* Partition: block_of[q] (n entries, caller-owned) = index of qubit q's block;
+ * blocks are numbered 0.. in order of their smallest qubit. */
+sv_status sv_pblock_partition(sv_pblock p, int *block_of);
+
+/* Block b's qubits in local bit order (qubits_out: at least n entries; bit j
+ * of the block state's index is qubit qubits_out[j]) and a borrowed handle to
+ * its state, valid until the next sv_pblock_run or destroy (any output may be
+ * NULL; queued gates are applied first). */
+sv_status sv_pblock_block(sv_pblock p, int b, int *qubits_out, int *nq_out, sv_state *state_out);
+
+/* Amplitudes <i|psi> of `count` global indices (idx: count*W words), each the
+ * product over blocks of the block amplitude at the block's bits of i,
+ * formed on the device in FP64. out: 2*count doubles (re, im). */
+sv_status sv_pblock_get_amplitudes(sv_pblock p, const uint64_t *idx, int64_t count, double *out);
+
+/* Terminal measurement of all n qubits, `shots` times: blocks are independent
+ * factors, so block number b (partition order) draws its own bits for shot s
+ * with the inverse-CDF sampler of sv_sample at counter b*shots + s, and the
+ * shot's outcome is the union of the blocks' bits. out: shots*W words
+ * (caller-owned). */
+sv_status sv_pblock_sample(sv_pblock p, int64_t shots, uint64_t seed, uint64_t *out);
+
+/* Expectation values of Pauli strings of up to n qubits: term t has masks
+ * xmask[t*W .. t*W+W-1] and zmask likewise (bit q: X / Z on qubit q, both:
+ * Y, P = i^{popcount(x & z)} X^x Z^z) and coefficient coeff[t] (coeff may be
+ * NULL: 1). On a product state <P> is the product of the blocks' <P_b> (one
+ * sv_expect per block that the term touches). out_each (nterms entries) and
+ * out_weighted as in sv_expect. */
+sv_status sv_pblock_expect(sv_pblock p, const uint64_t *xmask, const uint64_t *zmask, const double *coeff,
+                           int nterms, double *out_each, double *out_weighted);
 
 /* ----------------------------------------------------------- profiling */
 

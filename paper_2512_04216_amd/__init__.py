@@ -16,10 +16,10 @@ import numpy as np
 from . import _abi
 from ._abi import (  # noqa: F401
     COST_CLASSES, GATE_KIND, GATE_KINDS, OP_KIND, SV_C64, SV_C128, SV_FUSE_AUTO, SV_FUSE_TILED, SV_OP_ADJOINT,
-    SvError, check, load, sv_op, sv_pauli,
+    SV_PBLOCK_MAX_QUBITS, SvError, check, load, sv_op, sv_op_cond, sv_pauli,
 )
 
-__all__ = ["Context", "State", "Server", "ops_to_array", "terms_to_array", "SvError", "load",
+__all__ = ["Context", "State", "PBlock", "Server", "ops_to_array", "terms_to_array", "SvError", "load",
            "GATE_KIND", "SV_C64", "SV_C128", "SV_FUSE_TILED", "SV_FUSE_AUTO", "CostModel"]
 
 
@@ -35,16 +35,19 @@ def _dtype_code(dtype) -> int:
     raise ValueError("dtype must be complex64 or complex128")
 
 
-SV_OP_DTYPE = np.dtype([("kind", "<i4"), ("flags", "<i4"), ("q", "<i4", 3), ("pad", "<i4"), ("p", "<f8", 3)])
+SV_OP_DTYPE = np.dtype([("kind", "<i4"), ("flags", "<i4"), ("q", "<i4", 3), ("cond", "<i4"), ("p", "<f8", 3)])
 
 
 def ops_to_numpy(ops) -> np.ndarray:
-    """Gate list [(name, qubits, params[, adjoint])] -> numpy array laid out as sv_op."""
+    """Gate list [(name, qubits, params[, adjoint[, (clbit, value)]])] -> numpy
+    array laid out as sv_op; the fifth entry makes the gate conditional."""
     a = np.zeros(max(1, len(ops)), dtype=SV_OP_DTYPE)
     for i, op in enumerate(ops):
         a["kind"][i] = OP_KIND[op[0]]
         if len(op) > 3 and op[3]:
             a["flags"][i] = SV_OP_ADJOINT
+        if len(op) > 4 and op[4] is not None:
+            a["cond"][i] = sv_op_cond(int(op[4][0]), int(op[4][1]))
         q = op[1]
         a["q"][i, : len(q)] = q
         p = op[2]
@@ -344,6 +347,103 @@ class State:
             raise ValueError("state size mismatch")
         check(lib().sv_copy_in(self.handle, psi.ctypes.data, psi.nbytes))
         return self
+
+
+def _words(x: int, W: int) -> list:
+    return [(int(x) >> (64 * k)) & (2**64 - 1) for k in range(W)]
+
+
+class PBlock:
+    """A p-block state of n qubits (sv_pblock_*): blocks of qubits that have
+    interacted, merged by gates across blocks and split by measurements."""
+
+    def __init__(self, ctx: Context, n: int, dtype="c128"):
+        self.ctx = ctx
+        self.n = int(n)
+        self.W = (self.n + 63) // 64
+        self.dtype = _dtype_code(dtype)
+        h = ctypes.c_void_p()
+        check(lib().sv_pblock_create(ctx.handle, self.n, self.dtype, ctypes.byref(h)))
+        self.handle = h
+        self.clbits = 0
+
+    def close(self):
+        if getattr(self, "handle", None):
+            check(lib().sv_pblock_destroy(self.handle))
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def run(self, ops, seed: int = 0, fuse_k: int = 0) -> int:
+        """Run ops (gates, conditional gates, "measure", "reset"); returns the
+        classical bits after the call (kept across calls)."""
+        arr = ops_to_array(ops)
+        cl = ctypes.c_uint64(self.clbits)
+        check(lib().sv_pblock_run(self.handle, arr, len(ops), int(fuse_k), int(seed) & (2**64 - 1),
+                                  ctypes.byref(cl)))
+        self.clbits = cl.value
+        return self.clbits
+
+    def info(self):
+        """(number of blocks, qubits of the largest block, bytes of all block
+        states, most bytes held at once)"""
+        nb, big, by, pk = ctypes.c_int(), ctypes.c_int(), ctypes.c_uint64(), ctypes.c_uint64()
+        check(lib().sv_pblock_info(self.handle, ctypes.byref(nb), ctypes.byref(big), ctypes.byref(by),
+                                   ctypes.byref(pk)))
+        return nb.value, big.value, by.value, pk.value
+
+    def partition(self) -> np.ndarray:
+        out = np.zeros(self.n, dtype=np.int32)
+        check(lib().sv_pblock_partition(self.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int))))
+        return out
+
+    def block(self, b: int):
+        """(qubits in local bit order, copy of the block's amplitudes)"""
+        q = np.zeros(self.n, dtype=np.int32)
+        nq = ctypes.c_int()
+        st = ctypes.c_void_p()
+        check(lib().sv_pblock_block(self.handle, int(b), q.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                    ctypes.byref(nq), ctypes.byref(st)))
+        dt = np.complex64 if self.dtype == SV_C64 else np.complex128
+        out = np.empty(1 << nq.value, dtype=dt)
+        check(lib().sv_copy_out(st, out.ctypes.data, out.nbytes))
+        return [int(x) for x in q[: nq.value]], out
+
+    def amplitudes(self, idx) -> np.ndarray:
+        """<i|psi> for global indices given as Python ints (or a (count, W) uint64 array)."""
+        if isinstance(idx, np.ndarray) and idx.ndim == 2:
+            words = np.ascontiguousarray(idx, dtype=np.uint64)
+        else:
+            words = np.array([_words(i, self.W) for i in idx], dtype=np.uint64).reshape(-1, self.W)
+        cnt = words.shape[0]
+        out = np.zeros(2 * max(1, cnt), dtype=np.float64)
+        check(lib().sv_pblock_get_amplitudes(self.handle, words.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                             cnt, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out[: 2 * cnt].view(np.complex128)
+
+    def sample(self, shots: int, seed: int) -> np.ndarray:
+        """(shots, W) uint64 words: bit q % 64 of word q // 64 is qubit q."""
+        out = np.zeros((max(1, shots), self.W), dtype=np.uint64)
+        check(lib().sv_pblock_sample(self.handle, int(shots), int(seed) & (2**64 - 1),
+                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
+        return out[:shots]
+
+    def expect(self, terms):
+        """terms: [(xmask, zmask, coeff)] with Python-int masks -> (values, weighted sum)."""
+        nt = len(terms)
+        xs = np.array([_words(x, self.W) for x, _, _ in terms] or [[0] * self.W], dtype=np.uint64)
+        zs = np.array([_words(z, self.W) for _, z, _ in terms] or [[0] * self.W], dtype=np.uint64)
+        co = np.array([c for _, _, c in terms] or [0.0], dtype=np.float64)
+        vals = np.zeros(max(1, nt), dtype=np.float64)
+        w = ctypes.c_double()
+        U64P, DPt = ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double)
+        check(lib().sv_pblock_expect(self.handle, xs.ctypes.data_as(U64P), zs.ctypes.data_as(U64P),
+                                     co.ctypes.data_as(DPt), nt, vals.ctypes.data_as(DPt), ctypes.byref(w)))
+        return vals[:nt], w.value
 
 
 from .serving import Server  # noqa: E402,F401

@@ -33,6 +33,14 @@ GATE_KIND = {name: i for i, name in enumerate(GATE_KINDS)}
 # non-unitary op kinds (sv_run_shots only)
 SV_OP_MEASURE, SV_OP_RESET = 64, 65
 OP_KIND = dict(GATE_KIND, measure=SV_OP_MEASURE, reset=SV_OP_RESET)
+SV_PBLOCK_MAX_QUBITS = 1024
+
+
+def sv_op_cond(clbit: int, value: int) -> int:
+    """sv_op.cond of a gate applied only when classical bit `clbit` holds `value`."""
+    if not 0 <= clbit <= 63:
+        raise ValueError("classical bit out of range 0..63")
+    return 1 + clbit + 64 * (1 if value else 0)
 
 
 class sv_ctx_opts(ctypes.Structure):
@@ -42,7 +50,7 @@ class sv_ctx_opts(ctypes.Structure):
 
 class sv_op(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("flags", ctypes.c_int32), ("q", ctypes.c_int32 * 3),
-                ("pad", ctypes.c_int32), ("p", ctypes.c_double * 3)]
+                ("cond", ctypes.c_int32), ("p", ctypes.c_double * 3)]
 
 
 class sv_pauli(ctypes.Structure):
@@ -115,6 +123,15 @@ PROTOTYPES = {
     "sv_cost_coefficient": [P, I32, ctypes.c_double, DP],
     "sv_cost_predict": [P, ctypes.POINTER(sv_op), I32, I32, I32, I64, DP],
     "sv_ctx_set_cost_model": [P, P],
+    "sv_pblock_create": [P, I32, I32, ctypes.POINTER(P)],
+    "sv_pblock_destroy": [P],
+    "sv_pblock_run": [P, ctypes.POINTER(sv_op), I32, I32, U64, U64P],
+    "sv_pblock_info": [P, IP, IP, U64P, U64P],
+    "sv_pblock_partition": [P, IP],
+    "sv_pblock_block": [P, I32, IP, IP, ctypes.POINTER(P)],
+    "sv_pblock_get_amplitudes": [P, U64P, I64, DP],
+    "sv_pblock_sample": [P, I64, U64, U64P],
+    "sv_pblock_expect": [P, U64P, U64P, DP, I32, DP, DP],
     "sv_norm": [P, DP],
     "sv_renormalize": [P],
     "sv_sample": [P, I64, U64, U64P],

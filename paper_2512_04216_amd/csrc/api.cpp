@@ -260,10 +260,13 @@ sv_status apply_op(sv_state st, const sv_op &o) {
     return apply_matrix(st, U, k, o.q + nc, o.q, nc);
 }
 
-static sv_status validate_ops(sv_state st, const sv_op *ops, int nops) {
+static sv_status validate_ops(sv_state st, const sv_op *ops, int nops, bool allow_cond = false) {
     for (int i = 0; i < nops; ++i) {
         const int nq = gate_nqubits(ops[i].kind);
         if (nq < 0) return fail(SV_E_INVALID, "unknown gate kind at op " + std::to_string(i));
+        if (ops[i].cond != 0 && !(allow_cond && cond_valid(ops[i].cond)))
+            return fail(SV_E_INVALID, allow_cond ? "bad cond at op " + std::to_string(i)
+                                                 : "conditional op " + std::to_string(i) + " needs classical bits");
         uint64_t m = 0;
         sv_status r = check_qubits(st, ops[i].q, nq, &m);
         if (r) return fail(r, "op " + std::to_string(i) + ": " + g_err);
@@ -311,8 +314,7 @@ sv_status run_tiled(sv_state st, const sv_op *ops, int nops, After &after) {
 }
 
 // ---- shots with mid-circuit measurements ------------------------------------
-// The generator of the sampler (SplitMix64 at counter s, 53-bit uniform).
-static double host_u01(uint64_t seed, uint64_t s) {
+double host_u01(uint64_t seed, uint64_t s) {
     uint64_t z = seed + (s + 1ull) * 0x9E3779B97F4A7C15ull;
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
@@ -320,18 +322,9 @@ static double host_u01(uint64_t seed, uint64_t s) {
     return (double)(z >> 11) * 0x1.0p-53;
 }
 
-struct ShotScratch {
-    uint64_t *hmask = nullptr;   // pinned: 1 mask, then 2 results
-    double *hres = nullptr;
-    uint64_t *dmask = nullptr;   // device
-    double *dres = nullptr;
-    uint64_t *dcnt = nullptr, *dout = nullptr;   // device: counters and samples of one branch
-    uint64_t *hcnt = nullptr, *hout = nullptr;   // pinned
-};
-
 // FP64 probabilities of qubit q being 0 / 1 (the compensated Z pass gives
 // p0 - p1 and p0 + p1).
-static sv_status qubit_probs(sv_state st, int q, ShotScratch &w, double *p0, double *p1) {
+sv_status qubit_probs(sv_state st, int q, ShotScratch &w, double *p0, double *p1) {
     w.hmask[0] = 1ull << q;
     SV_HIP(hipMemcpyAsync(w.dmask, w.hmask, 8, hipMemcpyHostToDevice, st->stream));
     SV_HIP(svk::launch_expect_z(st->psi, st->n, st->is_c64(), w.dmask, 1, st->ws, w.dres, st->stream));
@@ -345,7 +338,7 @@ static sv_status qubit_probs(sv_state st, int q, ShotScratch &w, double *p0, dou
 
 // Project qubit q on outcome m and rescale by 1/sqrt(pm); with `reset` an
 // outcome 1 is moved back to |0>.
-static sv_status collapse(sv_state st, int q, int m, double pm, bool reset) {
+sv_status collapse(sv_state st, int q, int m, double pm, bool reset) {
     const double c = 1.0 / std::sqrt(pm);
     TraceScope ts(&st->ctx->tracer, st->stream, "collapse", 2.0 * (double)st->bytes);
     if (reset && m == 1) {
@@ -456,6 +449,19 @@ sv_status sv_create(sv_ctx c, int n, sv_dtype dt, sv_state *out) {
 }  // extern "C"
 
 sv_status svh::state_create(sv_ctx c, int n, sv_dtype dt, hipStream_t stream, sv_state *out) {
+    sv_state st = nullptr;
+    sv_status r = state_alloc(c, n, dt, stream, &st);
+    if (r) return r;
+    r = sv_reset(st, 0);
+    if (r != SV_OK) {
+        sv_destroy(st);
+        return r;
+    }
+    *out = st;
+    return SV_OK;
+}
+
+sv_status svh::state_alloc(sv_ctx c, int n, sv_dtype dt, hipStream_t stream, sv_state *out) {
     if (dt != SV_C64 && dt != SV_C128) return fail(SV_E_INVALID, "dtype must be SV_C64 or SV_C128");
     const int nmax = dt == SV_C64 ? SV_MAX_QUBITS_C64 : SV_MAX_QUBITS_C128;
     if (n < 1 || n > nmax) return fail(SV_E_INVALID, "n out of range [1, " + std::to_string(nmax) + "]");
@@ -480,11 +486,6 @@ sv_status svh::state_create(sv_ctx c, int n, sv_dtype dt, hipStream_t stream, sv
     {
         std::lock_guard<std::mutex> g(c->mu);
         c->nstates++;
-    }
-    sv_status r = sv_reset(st, 0);
-    if (r != SV_OK) {
-        sv_destroy(st);
-        return r;
     }
     *out = st;
     return SV_OK;
@@ -649,8 +650,8 @@ sv_status sv_run_shots(sv_state st, const sv_op *ops, int nops, int fuse_k, int6
                 return fail(SV_E_INVALID, "op " + std::to_string(i) + ": classical bit out of range 0..63");
             ++K;
         } else {
-            sv_status r = validate_ops(st, &o, 1);
-            if (r) return r;
+            sv_status r = validate_ops(st, &o, 1, true);
+            if (r) return fail(r, "op " + std::to_string(i) + ": " + sv_last_error());
         }
     }
     if (shots == 0) return SV_OK;
@@ -706,7 +707,21 @@ sv_status sv_run_shots(sv_state st, const sv_op *ops, int nops, int fuse_k, int6
         while (r == SV_OK) {
             if (b.op < nops && ops[b.op].kind != SV_OP_MEASURE && ops[b.op].kind != SV_OP_RESET) {
                 const int e = unitary_end(b.op);
-                r = sv_run(b.st, ops + b.op, e - b.op, fuse_k);
+                bool plain = true;
+                for (int i = b.op; i < e; ++i) plain = plain && ops[i].cond == 0;
+                if (plain) {
+                    r = sv_run(b.st, ops + b.op, e - b.op, fuse_k);
+                } else {
+                    // every shot of a branch holds the same classical bits
+                    const uint64_t cl = clbits_out[b.shots[0]];
+                    std::vector<sv_op> seg;
+                    for (int i = b.op; i < e; ++i)
+                        if (cond_met(ops[i].cond, cl)) {
+                            seg.push_back(ops[i]);
+                            seg.back().cond = 0;
+                        }
+                    r = sv_run(b.st, seg.data(), (int)seg.size(), fuse_k);
+                }
                 b.op = e;
                 continue;
             }

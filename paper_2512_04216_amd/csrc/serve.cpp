@@ -671,6 +671,7 @@ sv_status validate(sv_server s, const sv_circuit *c) {
         const sv_op &o = c->ops[i];
         const int nq = gate_nqubits(o.kind);
         if (nq < 0) return fail(SV_E_INVALID, "unknown gate kind at op " + std::to_string(i));
+        if (o.cond != 0) return fail(SV_E_INVALID, "conditional op " + std::to_string(i) + " needs classical bits");
         uint64_t m = 0;
         for (int j = 0; j < nq; ++j) {
             if (o.q[j] < 0 || o.q[j] >= c->n) return fail(SV_E_INVALID, "qubit out of range at op " + std::to_string(i));

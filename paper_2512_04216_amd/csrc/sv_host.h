@@ -216,6 +216,32 @@ sv_status renorm(sv_state st);        // psi <- psi / ||psi|| on the state's str
 sv_status state_release(sv_state st);
 // allocate a state on a given stream (sv_create uses the context's stream)
 sv_status state_create(sv_ctx c, int n, sv_dtype dt, hipStream_t stream, sv_state *out);
+// the same without initialising the amplitudes (the caller writes every one)
+sv_status state_alloc(sv_ctx c, int n, sv_dtype dt, hipStream_t stream, sv_state *out);
+
+// ---- mid-circuit measurement ----------------------------------------------
+// U01(seed, s): the sampler's generator (SplitMix64 at counter s, 53-bit uniform)
+double host_u01(uint64_t seed, uint64_t s);
+// small pinned / device buffers for qubit probabilities and branch draws
+struct ShotScratch {
+    uint64_t *hmask = nullptr;   // pinned: 1 mask, then 2 results
+    double *hres = nullptr;
+    uint64_t *dmask = nullptr;   // device
+    double *dres = nullptr;
+    uint64_t *dcnt = nullptr, *dout = nullptr;   // device: counters and samples of one branch
+    uint64_t *hcnt = nullptr, *hout = nullptr;   // pinned
+};
+// FP64 probabilities of qubit q (local bit) reading 0 / 1; synchronous
+sv_status qubit_probs(sv_state st, int q, ShotScratch &w, double *p0, double *p1);
+// project qubit q on outcome m and rescale by 1/sqrt(pm); reset moves an outcome 1 back to |0>
+sv_status collapse(sv_state st, int q, int m, double pm, bool reset);
+// sv_op.cond: 0 (always) or 1 + c + 64 v (classical bit c holds v)
+inline bool cond_valid(int32_t cond) { return cond >= 0 && cond <= 128; }
+inline bool cond_met(int32_t cond, uint64_t clbits) {
+    if (cond == 0) return true;
+    const int c = (cond - 1) & 63, v = (cond - 1) >> 6;
+    return ((clbits >> c) & 1ull) == (uint64_t)v;
+}
 uint64_t state_bytes(int n, sv_dtype dt);
 
 }  // namespace svh

@@ -174,6 +174,25 @@ struct PackedBatch {
     double *res;
 };
 
+// ---- p-block states ----
+// Global positions of one block's qubits: local index bit j is global qubit
+// gq[j] (bit gq[j] % 64 of word gq[j] / 64 of a W-word global index).
+struct BlockMap {
+    int nq = 0, W = 1;
+    int gq[40] = {0};
+};
+
+// out (2^(a+b) amplitudes) <- A (a qubits, low index bits) (x) B (b qubits).
+hipError_t launch_kron(const void *A, int a, const void *B, int b, void *out, int is_c64, hipStream_t s);
+// out (n-1 qubits) <- c * psi restricted to bit j == m, bit j removed.
+hipError_t launch_split(const void *psi, int n, int j, int m, double c, void *out, int is_c64, hipStream_t s);
+// acc[i] (FP64 complex) <- (first ? 1 : acc[i]) * psi[block bits of global index i]
+hipError_t launch_gather_mul(const void *psi, int is_c64, const BlockMap &m, const uint64_t *gidx_dev, int64_t count,
+                             double *acc_dev, int first, hipStream_t s);
+// out[s*W + w] (|)= global placement of the block's bits of local_dev[s]
+hipError_t launch_place_bits(const uint64_t *local_dev, int64_t cnt, const BlockMap &m, uint64_t *out_dev, int first,
+                             hipStream_t s);
+
 // Largest circuit of the packed kernel: 12 qubits complex128, 13 complex64
 // (the state plus leaf sums in one workgroup's LDS).
 int packed_max_qubits(int is_c64);

@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported(S):
 
 STRUCTS = {
     "sv_ctx_opts": ["device", "arena", "arena_bytes", "stream", "renorm_period"],
-    "sv_op": ["kind", "flags", "q", "pad", "p"],
+    "sv_op": ["kind", "flags", "q", "cond", "p"],
     "sv_pauli": ["xmask", "zmask", "coeff"],
     "sv_trace_rec": ["name", "launches", "seconds", "bytes"],
     "sv_server_opts": ["arena_bytes", "max_active", "small_qubits", "max_queue", "nstreams"],

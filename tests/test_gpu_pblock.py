@@ -1,0 +1,192 @@
+"""GPU parity of p-block states (sv_pblock_*) against the p-block oracle and
+the full-state path: partitions bit-exact, classical bits equal, amplitudes
+(products over blocks) within the state-vector tolerances, per-block samples
+and Pauli expectations, states of more than 64 qubits, memory against the
+monolithic state, and the error paths."""
+import numpy as np
+import pytest
+
+import workloads as W
+from conftest import infidelity
+from oracle import pblock as PB
+from test_oracle_pblock import _local_circuit
+
+pytestmark = pytest.mark.gpu
+
+
+def _amps_check(got, want, dtype):
+    if dtype == "c128":
+        assert np.max(np.abs(got - want)) <= 1e-12
+    else:
+        assert infidelity(got, want) <= 1e-5
+        assert np.max(np.abs(got - want)) <= 1e-3
+
+
+def _words(x, W_):
+    return [(x >> (64 * k)) & (2**64 - 1) for k in range(W_)]
+
+
+@pytest.mark.parametrize("fuse_k", [0, 5, -1])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [1, 5, 12, 14])
+def test_local_circuits_match_oracle(ctx, S, n, dtype, fuse_k):
+    ops = _local_circuit(n, 8 * n, seed=31 * n + 1, span=2)
+    _, want = PB.run(ops, n)
+    with S.PBlock(ctx, n, dtype) as pb:
+        pb.run(ops, fuse_k=fuse_k)
+        assert pb.partition().tolist() == want.partition().tolist()
+        nb, big, by, peak = pb.info()
+        assert nb == len(want.blocks) and big == max(len(q) for q, _ in want.blocks)
+        got = pb.amplitudes(list(range(1 << n)))
+    _amps_check(got, want.full_state(), dtype)
+
+
+@pytest.mark.parametrize("fuse_k", [0, 5, -1])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_distributed_circuit_matches_oracle(ctx, S, dtype, fuse_k):
+    ops, n = W.dqc(3, 4, 5, [(0, 1), (1, 2)], seed=17)
+    cl_want, want = PB.run(ops, n, seed=99)
+    with S.PBlock(ctx, n, dtype) as pb:
+        cl = pb.run(ops, seed=99, fuse_k=fuse_k)
+        assert cl == cl_want
+        assert pb.partition().tolist() == want.partition().tolist()
+        got = pb.amplitudes(list(range(1 << n)))
+        # each block's own state, through the borrowed handle, up to the local order
+        for b, (qs, psi) in enumerate(want.ordered()):
+            gq, gpsi = pb.block(b)
+            assert sorted(gq) == sorted(qs)
+            perm = [gq.index(q) for q in qs]
+            idx = [sum(((i >> j) & 1) << perm[j] for j in range(len(qs))) for i in range(1 << len(qs))]
+            _amps_check(gpsi.astype(np.complex128)[idx], psi, dtype)
+    _amps_check(got, want.full_state(), dtype)
+
+
+def test_split_of_every_position(ctx, S):
+    # a 10-qubit block, then each qubit measured in turn: every bit position is split out
+    n = 10
+    ops = W.brickwork(n, 6, seed=4) + [("measure", (q, q), ()) for q in (0, 9, 5, 1, 8, 2, 7, 3, 6, 4)]
+    cl_want, want = PB.run(ops, n, seed=5)
+    with S.PBlock(ctx, n, "c128") as pb:
+        cl = pb.run(ops, seed=5)
+        assert cl == cl_want and pb.info()[:2] == (n, 1)
+        got = pb.amplitudes(list(range(1 << n)))
+    _amps_check(got, want.full_state(), "c128")
+    assert abs(abs(got[cl]) - 1) <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_sampling_and_expectations_match_oracle(ctx, S, dtype):
+    ops, n = W.dqc(2, 5, 4, [(0, 1)], seed=23)
+    ops = ops + [("u3", (11,), (0.3, 0.2, 0.1)), ("ry", (10,), (1.1,))]
+    cl_want, want = PB.run(ops, n, seed=8)
+    shots = 3000
+    ref = want.sample(shots, 41)
+    terms = [(x, z, 0.5 + 0.1 * i) for i, (x, z, _) in enumerate(W.random_paulis(n, 10, 6))]
+    terms += [(0, 1 << 10, 1.0), (1 << 11, 1 << 11, -1.0), (0, 0, 2.0)]
+    with S.PBlock(ctx, n, dtype) as pb:
+        assert pb.run(ops, seed=8) == cl_want
+        smp = pb.sample(shots, 41)
+        vals, wsum = pb.expect(terms)
+    got = [int(w[0]) for w in smp]
+    bad = sum(1 for a, b in zip(got, ref) if a != b)
+    assert bad <= (1 if dtype == "c128" else shots // 100)
+    want_vals = np.array([want.expect(x, z) for x, z, _ in terms])
+    tol = 1e-12 if dtype == "c128" else 1e-5
+    assert np.max(np.abs(vals - want_vals)) <= tol
+    assert abs(wsum - float(np.dot([c for _, _, c in terms], want_vals))) <= 10 * tol
+    assert vals[-1] == 1.0
+
+
+def test_more_than_64_qubits(ctx, S, O):
+    # 9 hosts of 7 qubits, four links: 71 qubits, index words of two 64-bit halves
+    ops, n = W.dqc(9, 7, 3, [(0, 1), (2, 3), (4, 5), (7, 8)], seed=3)
+    assert n == 71
+    cl_want, want = PB.run(ops, n, seed=12)
+    rng = np.random.default_rng(2)
+    idx = [int(rng.integers(0, 2**63)) | (int(rng.integers(0, 2**7)) << 64) for _ in range(400)]
+    # indices on the support: the terminal samples of the oracle
+    idx += want.sample(200, 77)
+    shots = 500
+    ref = want.sample(shots, 5)
+    xs = [(int(rng.integers(0, 2**63)) | (1 << 70), int(rng.integers(0, 2**63)), 1.0) for _ in range(4)]
+    terms = [(x & ((1 << 71) - 1), z, c) for x, z, c in xs]
+    # a term on qubits of one entangled pair of hosts, so its value is far from zero
+    terms.append((0, (1 << 14) | (1 << 20), 1.0))
+    with S.PBlock(ctx, n, "c128") as pb:
+        assert pb.run(ops, seed=12) == cl_want
+        assert pb.partition().tolist() == want.partition().tolist()
+        got = pb.amplitudes(idx)
+        smp = pb.sample(shots, 5)
+        vals, _ = pb.expect(terms)
+        nb, big, by, peak = pb.info()
+    assert np.max(np.abs(got - np.array([want.amplitude(i) for i in idx]))) <= 1e-12
+    assert np.max(np.abs(got[400:])) > 0
+    gs = [int(w[0]) | (int(w[1]) << 64) for w in smp]
+    assert sum(1 for a, b in zip(gs, ref) if a != b) <= 1
+    assert np.max(np.abs(vals - [want.expect(x, z) for x, z, _ in terms])) <= 1e-12
+    assert big == 14 and by == want.state_bytes()
+
+
+def test_against_the_monolithic_state(ctx, S, O):
+    # two hosts of 10 qubits and one link: the monolithic state holds 22 qubits,
+    # the p-block one 20 after every protocol; once the hosts share a block, the
+    # entangled pair joins it for the cat-entangler (22 qubits), and the split
+    # that measures it out holds the 22- and the 21-qubit states at once
+    ops, n = W.dqc(2, 10, 4, [(0, 1)], seed=29)
+    seed = 314
+    with S.PBlock(ctx, n, "c128") as pb:
+        cl = pb.run(ops, seed=seed, fuse_k=-1)
+        nb, big, by, peak = pb.info()
+        rng = np.random.default_rng(3)
+        idx = [int(i) for i in rng.integers(0, 1 << n, 3000)]
+        got = pb.amplitudes(idx)
+    with S.State(ctx, n, "c128") as st:
+        cls, _ = st.run_shots(ops, 1, seed, fuse_k=-1)
+        mono = st.amplitudes(np.array(idx, dtype=np.uint64))
+    assert int(cls[0]) == cl
+    assert np.max(np.abs(got - mono)) <= 1e-12
+    assert big == 20 and by == 16 * ((1 << 20) + 2 * 2)
+    assert peak == 16 * ((1 << 22) + (1 << 21) + 2)
+
+
+def test_state_persists_across_runs(ctx, S):
+    n = 9
+    ops = _local_circuit(n, 60, seed=8, span=2)
+    half = len(ops) // 2
+    ops[half:half] = [("measure", (3, 0), ()), W.c_if(("x", (4,), ()), 0, 1)]
+    cl_want, want = PB.run(ops[: half + 2], n, seed=1)
+    cl_want, want = PB.run(ops[half + 2:], n, seed=2, state=want, clbits=cl_want)
+    with S.PBlock(ctx, n, "c128") as pb:
+        pb.run(ops[: half + 2], seed=1, fuse_k=5)
+        cl = pb.run(ops[half + 2:], seed=2, fuse_k=0)
+        got = pb.amplitudes(list(range(1 << n)))
+    assert cl == cl_want
+    _amps_check(got, want.full_state(), "c128")
+
+
+def test_errors(ctx, S):
+    with S.PBlock(ctx, 40, "c128") as pb:
+        chain = [("cx", (q, q + 1), ()) for q in range(16)] + [("cx", (q, q + 1), ()) for q in range(17, 33)]
+        pb.run(chain)
+        assert pb.info()[1] == 17
+        with pytest.raises(S.SvError, match="exceeds"):
+            pb.run([("cx", (16, 17), ())])          # 34 qubits in one block
+        with pytest.raises(S.SvError):
+            pb.run([("h", (40,), ())])              # qubit out of range
+        with pytest.raises(S.SvError):
+            pb.run([("measure", (0, 64), ())])      # classical bit out of range
+        arr = S.ops_to_numpy([("x", (0,), ())])
+        arr["cond"][0] = 200
+        with pytest.raises(S.SvError):
+            pb.run(arr)
+        with pytest.raises(S.SvError):
+            pb.expect([(1 << 40, 0, 1.0)])          # mask beyond n
+        with pytest.raises(S.SvError):
+            pb.amplitudes([1 << 40])
+        with pytest.raises(S.SvError):
+            pb.block(40)
+    with pytest.raises(S.SvError):
+        S.PBlock(ctx, 1025, "c128")
+    with S.State(ctx, 3, "c128") as st:
+        with pytest.raises(S.SvError, match="classical"):
+            st.run([W.c_if(("x", (0,), ()), 0, 1)])
