@@ -278,8 +278,9 @@ sv_status sv_pblock_destroy(sv_pblock p);
 /* Run ops in list order. Gates on one block queue up on it and run as sv_run
  * with fuse_k on the block's state when the block next merges, is measured
  * or is read, or when the call ends. A gate whose qubits lie in several blocks
- * merges them first (smaller block in the low index bits; the largest merged
- * block must fit SV_MAX_QUBITS_* and the arena). SV_OP_MEASURE / SV_OP_RESET:
+ * merges them first (the largest merged block must fit SV_MAX_QUBITS_* and
+ * the arena). Bit j of a block's amplitude index is always its j-th smallest
+ * qubit, whatever the order of the merges. SV_OP_MEASURE / SV_OP_RESET:
  * the k-th of the call (k = 0..K-1) draws u = U01(seed, k) and reads 1
  * exactly when u*(p0+p1) >= p0, with FP64 p0, p1 of the qubit in its block
  * (the trajectory of shot 0 of sv_run_shots with the same seed); the block
@@ -301,7 +302,7 @@ sv_status sv_pblock_info(sv_pblock p, int *nblocks, int *largest, uint64_t *stat
  * blocks are numbered 0.. in order of their smallest qubit. */
 sv_status sv_pblock_partition(sv_pblock p, int *block_of);
 
-/* Block b's qubits in local bit order (qubits_out: at least n entries; bit j
+/* Block b's qubits in ascending order (qubits_out: at least n entries; bit j
  * of the block state's index is qubit qubits_out[j]) and a borrowed handle to
  * its state, valid until the next sv_pblock_run or destroy (any output may be
  * NULL; queued gates are applied first). */
@@ -314,8 +315,9 @@ sv_status sv_pblock_get_amplitudes(sv_pblock p, const uint64_t *idx, int64_t cou
 
 /* Terminal measurement of all n qubits, `shots` times: blocks are independent
  * factors, so block number b (partition order) draws its own bits for shot s
- * with the inverse-CDF sampler of sv_sample at counter b*shots + s, and the
- * shot's outcome is the union of the blocks' bits. out: shots*W words
+ * with the inverse-CDF sampler of sv_sample on its state at counter
+ * b*shots + s, and the shot's outcome is the union of the blocks' bits (a
+ * single block of all n <= 64 qubits draws what sv_sample draws). out: shots*W words
  * (caller-owned). */
 sv_status sv_pblock_sample(sv_pblock p, int64_t shots, uint64_t seed, uint64_t *out);
 

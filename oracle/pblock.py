@@ -1,10 +1,11 @@
 """TEST INFRASTRUCTURE ONLY -- plain p-block oracle.
 
 Partitioned-block simulation (Sec. II, p-block; Sec. III-E, distributed
-circuits): the state is kept as a list of blocks, each a qubit list and a
-complex128 state vector of those qubits (bit j of a block's index is qubit
-qubits[j]). Every qubit starts in a block of its own; a gate whose qubits lie
-in several blocks first replaces them by their tensor product (numpy.kron); a
+circuits): the state is kept as a list of blocks, each an ascending qubit list
+and a complex128 state vector of those qubits (bit j of a block's index is its
+j-th smallest qubit). Every qubit starts in a block of its own; a gate whose
+qubits lie in several blocks first replaces them by their tensor product
+(numpy.kron, then the index bits put in ascending qubit order); a
 measured or reset qubit leaves its block, since the projected state is the
 qubit's basis state times the rest. Gates, probabilities and projections are
 the full-state oracle's routines applied to a block. Only the tests, the
@@ -15,6 +16,16 @@ from __future__ import annotations
 import numpy as np
 
 from . import oracle as O
+
+
+def _ascending(qs, psi):
+    """The same state with its index bits reordered so that bit j is the j-th
+    smallest qubit (bit j of psi's index is qubit qs[j] on entry)."""
+    nb = len(qs)
+    order = sorted(qs)
+    t = psi.reshape([2] * nb)                    # axis a <-> bit nb-1-a
+    axes = [nb - 1 - qs.index(order[nb - 1 - a]) for a in range(nb)]
+    return order, np.ascontiguousarray(np.transpose(t, axes).reshape(-1))
 
 
 class PBlockState:
@@ -43,8 +54,9 @@ class PBlockState:
             # kron(pb, psi)[ib * 2^len(qs) + ia] = pb[ib] * psi[ia]: qs stay the low bits
             psi = np.kron(pb, psi)
             qs = qs + qb
+        qs, psi = _ascending(qs, psi)
         keep = [b for i, b in enumerate(self.blocks) if i not in idx]
-        self.blocks = keep + [(qs, np.ascontiguousarray(psi))]
+        self.blocks = keep + [(qs, psi)]
         return len(self.blocks) - 1
 
     def gate(self, op):
@@ -94,10 +106,7 @@ class PBlockState:
         for qs, psi in self.blocks:
             out = np.kron(psi, out)
             order = order + qs
-        # out's bit j is qubit order[j]: move every bit to its global place
-        t = out.reshape([2] * self.n)            # axis a <-> bit n-1-a
-        axes = [self.n - 1 - order.index(self.n - 1 - a) for a in range(self.n)]
-        return np.ascontiguousarray(np.transpose(t, axes).reshape(-1))
+        return _ascending(order, out)[1]
 
     def sample(self, shots: int, seed: int):
         """Block b (partition order) draws shot s at counter b*shots + s; the

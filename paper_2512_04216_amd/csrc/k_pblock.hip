@@ -3,7 +3,7 @@
 // A p-block state keeps one state vector per group of qubits that have
 // interacted (Sec. II, p-block simulation): a gate across groups merges their
 // states into their tensor product, and a measured qubit leaves its group.
-//   k_kron:  out[iA + 2^a iB] = A[iA] * B[iB]          (merge of two groups)
+//   k_kron:  out[i] = A[A's bits of i] * B[B's bits of i] (merge of two groups)
 //   k_split: out[i'] = c * psi[i' with bit j set to m] (a measured qubit leaves)
 // Both stream their output once; every thread writes whole 16-byte slices.
 #include "sv_device.h"
@@ -11,6 +11,7 @@
 
 using namespace svd;
 using svk::BlockMap;
+using svk::KronPos;
 
 namespace {
 
@@ -21,12 +22,22 @@ __device__ inline Cx<T> mul(Cx<T> x, Cx<T> y) {
     return Cx<T>{x.re * y.re - x.im * y.im, x.re * y.im + x.im * y.re};
 }
 
+// Output bit pos.p[k] (ascending k) is bit k of A's index; the other bits,
+// in order, form B's index. Removing A's bits from the highest down keeps the
+// lower positions valid.
 template <typename T>
-__global__ __launch_bounds__(kB) void k_kron(const Cx<T> *__restrict__ A, int a, const Cx<T> *__restrict__ B,
+__global__ __launch_bounds__(kB) void k_kron(const Cx<T> *__restrict__ A, KronPos pos, const Cx<T> *__restrict__ B,
                                              uint64_t nout, Cx<T> *__restrict__ out) {
     const uint64_t stride = grid_blocks() * kB;
-    for (uint64_t i = block_linear() * kB + threadIdx.x; i < nout; i += stride)
-        out[i] = mul(A[i & ((1ull << a) - 1ull)], B[i >> a]);
+    for (uint64_t i = block_linear() * kB + threadIdx.x; i < nout; i += stride) {
+        uint64_t ia = 0, ib = i;
+        for (int k = pos.a - 1; k >= 0; --k) {
+            const int p = pos.p[k];
+            ia |= ((i >> p) & 1ull) << k;
+            ib = ((ib >> (p + 1)) << p) | (ib & ((1ull << p) - 1ull));
+        }
+        out[i] = mul(A[ia], B[ib]);
+    }
 }
 
 template <typename T>
@@ -92,15 +103,16 @@ dim3 grid_for(int64_t count) {
 
 namespace svk {
 
-hipError_t launch_kron(const void *A, int a, const void *B, int b, void *out, int is_c64, hipStream_t s) {
-    const uint64_t nout = 1ull << (a + b);
+hipError_t launch_kron(const void *A, const KronPos &pos, const void *B, int b, void *out, int is_c64,
+                       hipStream_t s) {
+    const uint64_t nout = 1ull << (pos.a + b);
     const dim3 g((unsigned)blocks_for(nout));
     if (is_c64)
-        hipLaunchKernelGGL(k_kron<float>, g, dim3(kB), 0, s, (const Cx<float> *)A, a, (const Cx<float> *)B, nout,
+        hipLaunchKernelGGL(k_kron<float>, g, dim3(kB), 0, s, (const Cx<float> *)A, pos, (const Cx<float> *)B, nout,
                            (Cx<float> *)out);
     else
-        hipLaunchKernelGGL(k_kron<double>, g, dim3(kB), 0, s, (const Cx<double> *)A, a, (const Cx<double> *)B, nout,
-                           (Cx<double> *)out);
+        hipLaunchKernelGGL(k_kron<double>, g, dim3(kB), 0, s, (const Cx<double> *)A, pos, (const Cx<double> *)B,
+                           nout, (Cx<double> *)out);
     return hipGetLastError();
 }
 

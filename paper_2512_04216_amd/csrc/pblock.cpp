@@ -3,12 +3,13 @@
 //
 // The state of n qubits is a tensor product of blocks; each block is an
 // ordinary device state (sv_state) of the qubits that have interacted. A gate
-// spanning several blocks merges them (k_kron, smaller block in the low index
-// bits so that the larger one streams through once); a measured or reset qubit
+// spanning several blocks merges them (k_kron); a measured or reset qubit
 // leaves its block (k_split projects, rescales and drops its bit in one pass),
 // so communication qubits return to blocks of their own as soon as a protocol
-// measures them. Gates on one block queue up and run as one sv_run call (per
-// gate, fused or tiled) when the block is next merged, measured or read.
+// measures them. A block's index bits hold its qubits in ascending order, so
+// its amplitudes, CDF and draws do not depend on the order of the merges.
+// Gates on one block queue up and run as one sv_run call (per gate, fused or
+// tiled) when the block is next merged, measured or read.
 #include "sv_host.h"
 
 #include <algorithm>
@@ -83,7 +84,7 @@ sv_status merge(sv_pblock p, PBlk *A, PBlk *B, PBlk **out) {
     sv_status r = flush(p, A);
     if (!r) r = flush(p, B);
     if (r) return r;
-    if (A->q.size() > B->q.size()) std::swap(A, B);   // smaller block in the low bits
+    if (A->q.size() > B->q.size()) std::swap(A, B);   // the kernel walks the smaller block's bits
     const int a = (int)A->q.size(), b = (int)B->q.size();
     const int nmax = p->dt == SV_C64 ? SV_MAX_QUBITS_C64 : SV_MAX_QUBITS_C128;
     if (a + b > nmax)
@@ -92,9 +93,16 @@ sv_status merge(sv_pblock p, PBlk *A, PBlk *B, PBlk **out) {
     sv_state st = nullptr;
     r = state_alloc(p->ctx, a + b, p->dt, p->ctx->stream, &st);
     if (r) return r;
+    // block qubits stay in ascending order: A's qubits take their places among B's
+    std::vector<int> mq(A->q);
+    mq.insert(mq.end(), B->q.begin(), B->q.end());
+    std::sort(mq.begin(), mq.end());
+    svk::KronPos pos;
+    pos.a = a;
+    for (int k = 0; k < a; ++k) pos.p[k] = (int)(std::lower_bound(mq.begin(), mq.end(), A->q[k]) - mq.begin());
     {
         TraceScope ts(&p->ctx->tracer, st->stream, "kron", (double)st->bytes + A->st->bytes + B->st->bytes);
-        hipError_t e = svk::launch_kron(A->st->psi, a, B->st->psi, b, st->psi, st->is_c64(), st->stream);
+        hipError_t e = svk::launch_kron(A->st->psi, pos, B->st->psi, b, st->psi, st->is_c64(), st->stream);
         if (e != hipSuccess) {
             hipStreamSynchronize(st->stream);
             state_release(st);
@@ -104,8 +112,7 @@ sv_status merge(sv_pblock p, PBlk *A, PBlk *B, PBlk **out) {
     hold(p, st);
     PBlk *M = new PBlk();
     M->st = st;
-    M->q = A->q;
-    M->q.insert(M->q.end(), B->q.begin(), B->q.end());
+    M->q = mq;
     // the sources' memory goes back to the arena; later users run on the same
     // stream, after the merge
     remove_block(p, A);

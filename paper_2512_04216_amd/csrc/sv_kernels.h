@@ -182,8 +182,15 @@ struct BlockMap {
     int gq[40] = {0};
 };
 
-// out (2^(a+b) amplitudes) <- A (a qubits, low index bits) (x) B (b qubits).
-hipError_t launch_kron(const void *A, int a, const void *B, int b, void *out, int is_c64, hipStream_t s);
+// Bit positions of the a qubits of A in the merged index (ascending).
+struct KronPos {
+    int a = 0;
+    int p[40] = {0};
+};
+// out (2^(a+b) amplitudes) <- A (x) B: bit pos.p[k] of out's index is bit k of
+// A's index, its other bits in order form B's index.
+hipError_t launch_kron(const void *A, const KronPos &pos, const void *B, int b, void *out, int is_c64,
+                       hipStream_t s);
 // out (n-1 qubits) <- c * psi restricted to bit j == m, bit j removed.
 hipError_t launch_split(const void *psi, int n, int j, int m, double c, void *out, int is_c64, hipStream_t s);
 // acc[i] (FP64 complex) <- (first ? 1 : acc[i]) * psi[block bits of global index i]

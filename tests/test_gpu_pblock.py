@@ -149,6 +149,24 @@ def test_against_the_monolithic_state(ctx, S, O):
     assert peak == 16 * ((1 << 22) + (1 << 21) + 2)
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_one_block_samples_like_the_full_state(ctx, S, dtype):
+    # a brickwork joins every qubit into one block, merged in scattered order
+    n = 16
+    perm = np.random.default_rng(1).permutation(n)
+    ops = [(o[0], tuple(int(perm[q]) for q in o[1]), o[2]) for o in W.brickwork(n, 8, seed=2)]
+    with S.PBlock(ctx, n, dtype) as pb:
+        pb.run(ops, fuse_k=5)
+        assert pb.info()[:2] == (1, n)
+        smp = pb.sample(4000, 19)[:, 0]
+        q, _ = pb.block(0)
+        assert q == list(range(n))
+    with S.State(ctx, n, dtype) as st:
+        st.run(ops, fuse_k=5)
+        ref = st.sample(4000, 19)
+    assert np.count_nonzero(smp != ref) <= (1 if dtype == "c128" else 40)
+
+
 def test_state_persists_across_runs(ctx, S):
     n = 9
     ops = _local_circuit(n, 60, seed=8, span=2)

@@ -180,3 +180,15 @@ def test_conditional_gates_in_the_full_oracle():
     assert abs(psi[0b10101] - 1) <= 1e-15
     cls, smp = O.run_shots(ops, 5, 7, 9)
     assert np.all(cls == 1) and np.all(smp == 0b10101)
+
+
+def test_blocks_hold_ascending_qubits_and_one_block_samples_like_the_full_state():
+    # merges in every order: (3, 1), then (0, 5), then the two blocks via (5, 3),
+    # then 2 and 4 joined last
+    ops = [("h", (3,), ()), ("cx", (3, 1), ()), ("ry", (5,), (0.4,)), ("cx", (5, 0), ()), ("cz", (5, 3), ()),
+           ("u3", (4,), (0.3, 1.0, 2.0)), ("swap", (4, 2), ()), ("cx", (2, 1), ()), ("ry", (0,), (1.3,))]
+    _, st = PB.run(ops, 6)
+    assert [qs for qs, _ in st.blocks] == [[0, 1, 2, 3, 4, 5]]
+    full = O.run(ops, 6)
+    assert np.max(np.abs(st.blocks[0][1] - full)) <= 1e-12
+    assert np.array_equal(np.array(st.sample(2000, 17), dtype=np.uint64), O.sample(full, 2000, 17))
