@@ -22,21 +22,33 @@ __device__ inline Cx<T> mul(Cx<T> x, Cx<T> y) {
     return Cx<T>{x.re * y.re - x.im * y.im, x.re * y.im + x.im * y.re};
 }
 
-// Output bit pos.p[k] (ascending k) is bit k of A's index; the other bits,
-// in order, form B's index. Removing A's bits from the highest down keeps the
-// lower positions valid.
+// Output bit pos.p[k] (ascending k) is bit k of A's index (A: the smaller
+// block); the other bits, in order, form B's index. Each work item reads one
+// amplitude of B once and writes the 2^cl outputs that pair it with 2^cl
+// consecutive amplitudes of A (A stays in cache), so B streams through
+// exactly once however A's bits interleave with B's.
+constexpr int kMaxCl = 4;   // at most 16 outputs per item
+
 template <typename T>
 __global__ __launch_bounds__(kB) void k_kron(const Cx<T> *__restrict__ A, KronPos pos, const Cx<T> *__restrict__ B,
-                                             uint64_t nout, Cx<T> *__restrict__ out) {
+                                             int b, int cl, uint64_t nitems, Cx<T> *__restrict__ out) {
     const uint64_t stride = grid_blocks() * kB;
-    for (uint64_t i = block_linear() * kB + threadIdx.x; i < nout; i += stride) {
-        uint64_t ia = 0, ib = i;
-        for (int k = pos.a - 1; k >= 0; --k) {
+    const uint64_t bmask = (1ull << b) - 1ull;
+    for (uint64_t t = block_linear() * kB + threadIdx.x; t < nitems; t += stride) {
+        const uint64_t ib = t & bmask, c = t >> b;
+        const Cx<T> v = B[ib];
+        // B's index bits spread over the positions A does not take
+        uint64_t base = ib;
+        for (int k = 0; k < pos.a; ++k) {
             const int p = pos.p[k];
-            ia |= ((i >> p) & 1ull) << k;
-            ib = ((ib >> (p + 1)) << p) | (ib & ((1ull << p) - 1ull));
+            base = ((base >> p) << (p + 1)) | (base & ((1ull << p) - 1ull));
         }
-        out[i] = mul(A[ia], B[ib]);
+        for (int kk = 0; kk < (1 << cl); ++kk) {
+            const uint64_t ka = (c << cl) | (uint64_t)kk;
+            uint64_t off = 0;
+            for (int k = 0; k < pos.a; ++k) off |= ((ka >> k) & 1ull) << pos.p[k];
+            out[base | off] = mul(A[ka], v);
+        }
     }
 }
 
@@ -105,14 +117,15 @@ namespace svk {
 
 hipError_t launch_kron(const void *A, const KronPos &pos, const void *B, int b, void *out, int is_c64,
                        hipStream_t s) {
-    const uint64_t nout = 1ull << (pos.a + b);
-    const dim3 g((unsigned)blocks_for(nout));
+    const int cl = std::min(pos.a, kMaxCl);
+    const uint64_t nitems = 1ull << (pos.a - cl + b);
+    const dim3 g((unsigned)blocks_for(nitems));
     if (is_c64)
-        hipLaunchKernelGGL(k_kron<float>, g, dim3(kB), 0, s, (const Cx<float> *)A, pos, (const Cx<float> *)B, nout,
-                           (Cx<float> *)out);
+        hipLaunchKernelGGL(k_kron<float>, g, dim3(kB), 0, s, (const Cx<float> *)A, pos, (const Cx<float> *)B, b, cl,
+                           nitems, (Cx<float> *)out);
     else
-        hipLaunchKernelGGL(k_kron<double>, g, dim3(kB), 0, s, (const Cx<double> *)A, pos, (const Cx<double> *)B,
-                           nout, (Cx<double> *)out);
+        hipLaunchKernelGGL(k_kron<double>, g, dim3(kB), 0, s, (const Cx<double> *)A, pos, (const Cx<double> *)B, b,
+                           cl, nitems, (Cx<double> *)out);
     return hipGetLastError();
 }
 
