@@ -323,3 +323,64 @@ void or_expect(const cplx *psi, int n, uint64_t xmask, uint64_t zmask,
     *re_out = neum_value(&sr) / nrm;
     *im_out = neum_value(&si) / nrm;
 }
+
+/* --------------------------------------------------------- alias sampling */
+
+/* Walker's alias method (the paper's sampler, Sec. III-C item 1): with
+ * N = 2^n and s_i = N p_i / W (p_i = |psi_i|^2, W their Neumaier sum), every
+ * slot i keeps its own outcome with probability prob[i] and otherwise yields
+ * alias[i], and slot masses add up to s_i. The table is built by one sweep in
+ * index order: entries with s_i < 1 are light, the others heavy; each light
+ * entry, in index order, takes the current heavy entry as its alias, and the
+ * heavy entry gives up what the light one lacks (1 - s_i); a heavy entry whose
+ * remaining mass r falls below 1 becomes light itself (prob r) and takes the
+ * next heavy entry as its alias, which gives up 1 - r. The last heavy entry
+ * (and any never reached) keeps prob 1. With no heavy entry (a distribution
+ * uniform up to rounding) every slot keeps its own outcome. */
+void or_alias_build(const cplx *psi, int n, double *prob, uint64_t *alias)
+{
+    const uint64_t N = 1ull << n;
+    const double scale = (double)N / or_norm2(psi, n);
+    uint64_t *L = malloc(N * sizeof(uint64_t)), *H = malloc(N * sizeof(uint64_t));
+    uint64_t nl = 0, nh = 0;
+    for (uint64_t i = 0; i < N; i++) {
+        double re = creal(psi[i]), im = cimag(psi[i]);
+        prob[i] = (re * re + im * im) * scale;
+        alias[i] = i;
+        if (prob[i] < 1.0) L[nl++] = i;
+        else H[nh++] = i;
+    }
+    if (nh == 0) {
+        for (uint64_t i = 0; i < N; i++) prob[i] = 1.0;
+    } else {
+        uint64_t j = 0;
+        double r = prob[H[0]];
+        for (uint64_t k = 0; k < nl; k++) {
+            alias[L[k]] = H[j];
+            r -= 1.0 - prob[L[k]];
+            while (r < 1.0 && j + 1 < nh) {
+                prob[H[j]] = r;
+                alias[H[j]] = H[j + 1];
+                j++;
+                r = prob[H[j]] - (1.0 - r);
+            }
+        }
+        for (uint64_t t = j; t < nh; t++) prob[H[t]] = 1.0;
+    }
+    free(L);
+    free(H);
+}
+
+/* Draws of the alias table: shot s (counter c = s0 + s) takes the slot
+ * floor(u1 N) with u1 = U01(seed, 2c) and keeps it when U01(seed, 2c + 1) <
+ * prob[slot], else returns alias[slot]. */
+void or_alias_sample(const double *prob, const uint64_t *alias, int n, int64_t count, uint64_t seed,
+                     uint64_t s0, uint64_t *out)
+{
+    const double N = (double)(1ull << n);
+    for (int64_t s = 0; s < count; s++) {
+        const uint64_t c = s0 + (uint64_t)s;
+        const uint64_t slot = (uint64_t)(or_u01(seed, 2 * c) * N);
+        out[s] = (or_u01(seed, 2 * c + 1) < prob[slot]) ? slot : alias[slot];
+    }
+}

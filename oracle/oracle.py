@@ -70,6 +70,11 @@ def lib():
         L.or_collapse.argtypes = [_c_cplx_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                   ctypes.c_int]
         L.or_collapse.restype = None
+        L.or_alias_build.argtypes = [_c_cplx_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+        L.or_alias_build.restype = None
+        L.or_alias_sample.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int64,
+                                      ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p]
+        L.or_alias_sample.restype = None
         _lib = L
     return _lib
 
@@ -247,6 +252,25 @@ def run_shots(ops, n: int, shots: int, seed: int, basis: int = 0, psi: np.ndarra
         clbits[s] = np.uint64(cl)
         samples[s] = sample_at(st, [s * (K + 1) + K], seed)[0]
     return clbits, samples
+
+
+def alias_build(psi: np.ndarray):
+    """Walker alias table (prob, alias) of |psi|^2, built by one sweep in index order."""
+    n = _check_state(psi)
+    prob = np.empty(psi.size, dtype=np.float64)
+    alias = np.empty(psi.size, dtype=np.uint64)
+    lib().or_alias_build(_ptr(psi), n, _ptr(prob), _ptr(alias))
+    return prob, alias
+
+
+def alias_sample(prob: np.ndarray, alias: np.ndarray, shots: int, seed: int, s0: int = 0) -> np.ndarray:
+    """Shot s: slot floor(U01(seed, 2c) N), kept when U01(seed, 2c+1) < prob[slot], c = s0 + s."""
+    prob = np.ascontiguousarray(prob, dtype=np.float64)
+    alias = np.ascontiguousarray(alias, dtype=np.uint64)
+    n = int(prob.size).bit_length() - 1
+    out = np.empty(shots, dtype=np.uint64)
+    lib().or_alias_sample(_ptr(prob), _ptr(alias), n, int(shots), seed & (2**64 - 1), int(s0), _ptr(out))
+    return out
 
 
 def expect(psi: np.ndarray, xmask: int, zmask: int):
