@@ -239,6 +239,22 @@ sv_status sv_renormalize(sv_state st);
  * shot order. shots may be 0. */
 sv_status sv_sample(sv_state st, int64_t shots, uint64_t seed, uint64_t *out);
 
+/* Terminal measurement by Walker's alias method (Sec. III-C item 1: O(1) per
+ * shot after an O(2^n) table). With N = 2^n and s_i = N |psi_i|^2 / W (W the
+ * compensated squared norm), slot i keeps outcome i with probability prob[i]
+ * and otherwise yields alias[i]; the table is the one of the sweep
+ * construction in index order (entries with s_i < 1 take the current entry
+ * with s_i >= 1 as alias; such an entry whose excess runs out takes the next
+ * one), computed on the device from compensated prefix sums. Shot s draws
+ * u1 = U01(seed, 2s), u2 = U01(seed, 2s+1) (the generator of sv_sample),
+ * takes slot floor(u1 N) and returns the slot if u2 < prob[slot], else its
+ * alias. out (caller-owned, `shots` entries) receives the outcomes; prob_out
+ * and alias_out (nullable, N entries each, caller-owned) receive the table.
+ * The table and its build scratch, 40 bytes per amplitude, are taken from the
+ * arena for the call (SV_E_OOM if they do not fit). Synchronous. */
+sv_status sv_sample_alias(sv_state st, int64_t shots, uint64_t seed, uint64_t *out, double *prob_out,
+                          uint64_t *alias_out);
+
 /* One Pauli string P = i^{popcount(x & z)} X^x Z^z (bit q of xmask/zmask: X or Z
  * on qubit q; both set: Y), with a real coefficient. */
 typedef struct {

@@ -319,6 +319,19 @@ class State:
                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
         return out[:shots]
 
+    def sample_alias(self, shots: int, seed: int, table: bool = False):
+        """Shots by Walker's alias method (sv_sample_alias); with table=True
+        also returns the table (prob, alias)."""
+        out = np.zeros(max(1, shots), dtype=np.uint64)
+        N = 1 << self.n
+        prob = np.zeros(N, dtype=np.float64) if table else None
+        alias = np.zeros(N, dtype=np.uint64) if table else None
+        U64P, DPt = ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double)
+        check(lib().sv_sample_alias(self.handle, int(shots), int(seed) & (2**64 - 1), out.ctypes.data_as(U64P),
+                                    prob.ctypes.data_as(DPt) if table else None,
+                                    alias.ctypes.data_as(U64P) if table else None))
+        return (out[:shots], prob, alias) if table else out[:shots]
+
     def expect(self, terms):
         """terms: [(xmask, zmask, coeff)] -> (values, weighted sum)."""
         arr = terms_to_array(terms)

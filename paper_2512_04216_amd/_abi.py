@@ -135,6 +135,7 @@ PROTOTYPES = {
     "sv_norm": [P, DP],
     "sv_renormalize": [P],
     "sv_sample": [P, I64, U64, U64P],
+    "sv_sample_alias": [P, I64, U64, U64P, DP, U64P],
     "sv_expect": [P, ctypes.POINTER(sv_pauli), I32, DP, DP],
     "sv_trace_enable": [P, I32],
     "sv_trace_read": [P, ctypes.POINTER(sv_trace_rec), I32, IP],

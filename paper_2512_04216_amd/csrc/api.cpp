@@ -911,6 +911,53 @@ sv_status sv_sample(sv_state st, int64_t shots, uint64_t seed, uint64_t *out) {
     return r;
 }
 
+sv_status sv_sample_alias(sv_state st, int64_t shots, uint64_t seed, uint64_t *out, double *prob_out,
+                          uint64_t *alias_out) {
+    if (!st || shots < 0) return fail(SV_E_INVALID, "bad argument");
+    if (shots > 0 && !out) return fail(SV_E_INVALID, "null output");
+    sv_ctx c = st->ctx;
+    const uint64_t N = 1ull << st->n;
+    void *aws = c->arena.alloc(svk::alias_workspace_bytes(st->n));
+    if (!aws) return fail(SV_E_OOM, "arena cannot hold the alias table and its scratch");
+    sv_status r = SV_OK;
+    hipError_t e;
+    {
+        TraceScope ts(&c->tracer, st->stream, "alias_build", 41.0 * N + (double)st->bytes * 3.0);
+        e = svk::launch_alias_build(st->psi, st->n, st->is_c64(), st->ws, aws, st->stream);
+    }
+    double total = 0;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&total, svk::norm2_dev_ptr(st->ws, st->n), 8, hipMemcpyDeviceToHost, st->stream);
+    int64_t chunk = std::min<int64_t>(std::max<int64_t>(shots, 1), 1 << 22);
+    uint64_t *dev = nullptr;
+    while (e == hipSuccess && shots > 0 && !(dev = (uint64_t *)c->arena.alloc(chunk * sizeof(uint64_t)))) {
+        if (chunk <= 1024) break;
+        chunk /= 2;
+    }
+    if (e == hipSuccess && shots > 0 && !dev) r = fail(SV_E_OOM, "arena cannot hold the shot buffer");
+    for (int64_t s0 = 0; s0 < shots && e == hipSuccess && r == SV_OK; s0 += chunk) {
+        const int64_t cnt = std::min(chunk, shots - s0);
+        {
+            TraceScope ts(&c->tracer, st->stream, "alias_draw", 24.0 * cnt);
+            e = svk::launch_alias_draw(aws, st->n, cnt, seed, (uint64_t)s0, dev, st->stream);
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(out + s0, dev, cnt * sizeof(uint64_t), hipMemcpyDeviceToHost, st->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(st->stream);
+    }
+    if (e == hipSuccess && prob_out)
+        e = hipMemcpyAsync(prob_out, svk::alias_prob(aws), 8 * N, hipMemcpyDeviceToHost, st->stream);
+    if (e == hipSuccess && alias_out)
+        e = hipMemcpyAsync(alias_out, svk::alias_alias(aws, st->n), 8 * N, hipMemcpyDeviceToHost, st->stream);
+    hipError_t e2 = hipStreamSynchronize(st->stream);
+    if (e == hipSuccess) e = e2;
+    if (dev) c->arena.free(dev);
+    c->arena.free(aws);
+    if (e != hipSuccess) return hip_fail(e, "alias sampling");
+    if (r) return r;
+    if (!(total > 0.0)) return fail(SV_E_NUMERIC, "state has zero norm");
+    return SV_OK;
+}
+
 sv_status sv_expect(sv_state st, const sv_pauli *terms, int nterms, double *out_each, double *out_weighted) {
     if (!st || (nterms > 0 && !terms) || nterms < 0) return fail(SV_E_INVALID, "bad argument");
     const uint64_t full = st->n == 64 ? ~0ull : ((1ull << st->n) - 1);

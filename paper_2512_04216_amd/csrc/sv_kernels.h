@@ -174,6 +174,18 @@ struct PackedBatch {
     double *res;
 };
 
+// ---- Walker alias tables ----
+// Device workspace of an alias table of n qubits: prob (FP64) and alias
+// (uint64) per outcome first, then the build's scratch (40 B per outcome).
+uint64_t alias_workspace_bytes(int n);
+const double *alias_prob(const void *aws);
+const uint64_t *alias_alias(const void *aws, int n);
+// Table of |psi|^2 (the norm pass uses ws, the measurement workspace).
+hipError_t launch_alias_build(const void *psi, int n, int is_c64, void *ws, void *aws, hipStream_t s);
+// Shot s (counter s0 + s) from the table: out_dev[s].
+hipError_t launch_alias_draw(const void *aws, int n, int64_t shots, uint64_t seed, uint64_t s0, uint64_t *out_dev,
+                             hipStream_t s);
+
 // ---- p-block states ----
 // Global positions of one block's qubits: local index bit j is global qubit
 // gq[j] (bit gq[j] % 64 of word gq[j] / 64 of a W-word global index).
