@@ -344,6 +344,46 @@ def bench_pblock(S, m=15, rounds=8):
     return out
 
 
+def bench_sampling(S, sizes=(16, 20, 24, 28), shot_counts=(10**4, 10**6, 10**7)):
+    """Terminal sampling of a brickwork state (complex128): the FP64 inverse
+    CDF (sv_sample: one CDF pass, then a binary search and a leaf scan per
+    shot) against Walker's alias method (sv_sample_alias: a table build of
+    O(2^n), then O(1) per shot). Each time includes its build."""
+    import torch
+
+    import workloads as W
+
+    ctx = S.Context(arena_bytes=24 << 30)
+    out = {}
+    for n in sizes:
+        st = S.State(ctx, n, "c128")
+        st.run(W.brickwork(n, 6, seed=SEED + n))
+        row = {}
+        for shots in shot_counts:
+            st.sample(min(shots, 1000), 1)            # warm both paths
+            st.sample_alias(min(shots, 1000), 1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st.sample(shots, SEED)
+            t_cdf = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            st.sample_alias(shots, SEED)
+            t_alias = time.perf_counter() - t0
+            row[str(shots)] = {"cdf_ms": round(1e3 * t_cdf, 2), "alias_ms": round(1e3 * t_alias, 2)}
+        ctx.trace_read()
+        ctx.trace(True)
+        st.sample_alias(10**6, SEED)
+        ctx.trace(False)
+        tr = ctx.trace_read()
+        b = tr.get("alias_build")
+        row["alias_build_ms"] = round(1e3 * b["seconds"] / max(1, b["launches"]), 3) if b else None
+        out["n%d" % n] = row
+        st.close()
+        print("bench: sampling n = %d done" % n, file=sys.stderr, flush=True)
+    ctx.close()
+    return out
+
+
 def bench_small(S, reps=200, batch=2000):
     """12-qubit brickwork, 20 layers (350 gates), complex128, 1024 shots: a
     latency-bound circuit (the whole state is 64 KiB). Microseconds per
@@ -523,7 +563,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c64", action="store_true", help="skip the complex64 side measurement")
     ap.add_argument("--no-trace", action="store_true")
-    ap.add_argument("--config", default="28q", choices=["28q", "small", "fused", "qaoa", "serving", "cost", "pblock"],
+    ap.add_argument("--config", default="28q", choices=["28q", "small", "fused", "qaoa", "serving", "cost", "pblock", "sampling"],
                     help="28q (default): the headline line; the others print their own JSON line")
     ap.add_argument("--serving-count", type=int, default=10000)
     args = ap.parse_args()
@@ -541,7 +581,7 @@ def main():
         fn = {"fused": lambda: bench_fused(S), "qaoa": lambda: bench_qaoa(S),
               "serving": lambda: bench_serving(S, count=args.serving_count),
               "small": lambda: bench_small(S), "cost": lambda: bench_cost(S),
-              "pblock": lambda: bench_pblock(S)}[args.config]
+              "pblock": lambda: bench_pblock(S), "sampling": lambda: bench_sampling(S)}[args.config]
         print(json.dumps({"config": args.config, "result": fn()}))
         return
     print("bench: 28-qubit brickwork + QFT, %s, %d warmup + %d timed steps" % (args.dtype, args.warmup, args.steps),
