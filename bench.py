@@ -238,6 +238,35 @@ def bench_fused(S, steps=1):
     return out
 
 
+def bench_fused_mfma(S):
+    """Fused blocks only (fuse_k = 5), 30-qubit complex128 and 31-qubit complex64
+    brickwork, 10 layers: the workload the MFMA and HBM counters are read on.
+    A 4 GiB device copy runs first as the byte counters' calibration."""
+    import torch
+
+    import workloads as W
+
+    stream_copy_gbps(reps=1)
+    ctx = S.Context(arena_bytes=24 << 30)
+    out = {}
+    for n, dt in ((30, "c128"), (31, "c64")):
+        ops = W.brickwork(n, 10, seed=SEED + 2)
+        arr = S.ops_to_numpy(ops)
+        with S.State(ctx, n, dt) as st:
+            st.run(arr, fuse_k=5)                     # warm
+            st.reset(0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st.run(arr, fuse_k=5)
+            torch.cuda.synchronize()
+            dt_s = time.perf_counter() - t0
+        out["%dq_%s" % (n, dt)] = {"gates": len(ops), "blocks": S.sv_plan_fusion(ops, n, 5)[0],
+                                    "seconds": round(dt_s, 4)}
+        print("bench fused_mfma: %dq %s %.3f s" % (n, dt, dt_s), file=sys.stderr, flush=True)
+    ctx.close()
+    return out
+
+
 def bench_qaoa(S):
     """30-qubit QAOA MaxCut p=20 on a seeded random 3-regular graph; energy
     <H_cost> = sum over edges of <Z_u Z_v>, complex64 vs complex128."""
@@ -563,7 +592,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c64", action="store_true", help="skip the complex64 side measurement")
     ap.add_argument("--no-trace", action="store_true")
-    ap.add_argument("--config", default="28q", choices=["28q", "small", "fused", "qaoa", "serving", "cost", "pblock", "sampling"],
+    ap.add_argument("--config", default="28q", choices=["28q", "small", "fused", "fused_mfma", "qaoa", "serving", "cost", "pblock", "sampling"],
                     help="28q (default): the headline line; the others print their own JSON line")
     ap.add_argument("--serving-count", type=int, default=10000)
     args = ap.parse_args()
@@ -578,7 +607,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.config != "28q":
-        fn = {"fused": lambda: bench_fused(S), "qaoa": lambda: bench_qaoa(S),
+        fn = {"fused": lambda: bench_fused(S), "fused_mfma": lambda: bench_fused_mfma(S), "qaoa": lambda: bench_qaoa(S),
               "serving": lambda: bench_serving(S, count=args.serving_count),
               "small": lambda: bench_small(S), "cost": lambda: bench_cost(S),
               "pblock": lambda: bench_pblock(S), "sampling": lambda: bench_sampling(S)}[args.config]
