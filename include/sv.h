@@ -303,8 +303,10 @@ sv_status sv_pblock_destroy(sv_pblock p);
  * is projected and rescaled by 1/sqrt(p_m), and when it holds other qubits
  * the qubit leaves it in the basis state |m> (|0> after a reset) while the
  * rest keeps the projected amplitudes. *clbits (in/out, one word) holds the
- * classical bits: SV_OP_COND gates test it, SV_OP_MEASURE writes it.
- * Synchronous. */
+ * classical bits: SV_OP_COND gates test it, SV_OP_MEASURE writes it. The op
+ * list is validated before anything runs; an error while running (SV_E_OOM,
+ * a block beyond the size limit) leaves the state partly updated and drops
+ * the gates still queued. Synchronous. */
 sv_status sv_pblock_run(sv_pblock p, const sv_op *ops, int nops, int fuse_k, uint64_t seed,
                         uint64_t *clbits);
 

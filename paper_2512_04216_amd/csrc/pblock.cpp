@@ -326,6 +326,8 @@ sv_status sv_pblock_run(sv_pblock p, const sv_op *ops, int nops, int fuse_k, uin
         B->pending.push_back(l);
     }
     if (!r) r = flush_all(p);
+    if (r)   // gates queued before the failing op are dropped, not run by a later call
+        for (PBlk *b : p->blocks) b->pending.clear();
     hipError_t e = hipStreamSynchronize(p->ctx->stream);
     if (!r && e != hipSuccess) r = hip_fail(e, "p-block run");
     return r;
