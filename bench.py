@@ -557,6 +557,18 @@ def bench_serving(S, count=10000, baseline_count=300, loads=(0.5, 0.8, 0.95)):
         print("bench serving: saturated fuse_k=%d %s" % (fk, r), file=sys.stderr, flush=True)
         if best is None or r["circuits_per_s"] > best[1]["circuits_per_s"]:
             best = (fk, r)
+    # the cost model picks each request's mode (SV_FUSE_AUTO): calibrate on this
+    # device for the stream's qubit range, then serve the same stream
+    t0 = time.perf_counter()
+    model = S.CostModel.calibrate(ctx, "c64", 8, 26)
+    t_cal = time.perf_counter() - t0
+    ctx.set_cost_model(model)
+    r = run(S.SV_FUSE_AUTO)
+    r["calibration_s"] = round(t_cal, 2)
+    out["saturated_auto"] = r
+    print("bench serving: saturated auto %s" % r, file=sys.stderr, flush=True)
+    ctx.set_cost_model(None)
+    model.close()
     fk, sat = best
     for ld in loads:
         rate = ld * sat["circuits_per_s"]
