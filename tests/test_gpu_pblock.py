@@ -208,3 +208,28 @@ def test_errors(ctx, S):
     with S.State(ctx, 3, "c128") as st:
         with pytest.raises(S.SvError, match="classical"):
             st.run([W.c_if(("x", (0,), ()), 0, 1)])
+
+
+def test_edge_cases_up_to_1024_qubits(ctx, S):
+    n = 1024
+    ops = [("h", (1023,), ()), ("cx", (1023, 0), ()), ("ry", (512,), (0.7,)), ("cz", (512, 511), ()),
+           ("x", (700,), ()), ("measure", (700, 3), ()), ("reset", (700,), ()), ("cx", (1023, 1022), ())]
+    cl_want, want = PB.run(ops, n, seed=4)
+    with S.PBlock(ctx, n, "c128") as pb:
+        assert pb.run([], seed=1) == 0                       # an empty op list changes nothing
+        assert pb.info()[:2] == (n, 1)
+        assert pb.run(ops, seed=4) == cl_want == 1 << 3
+        assert pb.partition().tolist() == want.partition().tolist()
+        nb, big, by, peak = pb.info()
+        assert (nb, big) == (len(want.blocks), 3) and by == want.state_bytes()
+        idx = [0, (1 << 1023) | (1 << 1022) | 1, (1 << 512) | (1 << 1023) | (1 << 1022) | 1, 1 << 700]
+        got = pb.amplitudes(idx)
+        smp = pb.sample(300, 9)
+        vals, _ = pb.expect([(0, (1 << 1023) | 1, 1.0), (1 << 512, 0, 1.0), (0, 1 << 700, 1.0), (0, 0, 1.0)])
+    assert np.max(np.abs(got - np.array([want.amplitude(i) for i in idx]))) <= 1e-12
+    assert smp.shape == (300, 16)
+    ref = want.sample(300, 9)
+    gs = [sum(int(w[k]) << (64 * k) for k in range(16)) for w in smp]
+    assert gs == ref
+    assert np.max(np.abs(vals - [want.expect(x, z) for x, z, _ in
+                                 [(0, (1 << 1023) | 1, 1), (1 << 512, 0, 1), (0, 1 << 700, 1), (0, 0, 1)]])) <= 1e-12
