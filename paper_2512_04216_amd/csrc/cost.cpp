@@ -73,8 +73,8 @@ int gate_class(const GateDesc &d) {
 // flips (a phase pattern, a control on a tile qubit); run terms are part of
 // their run's one sweep.
 int record_class(const svk::TileGate &g) {
-    if (g.kind == 3) return -1;
-    const bool full = g.kind == 2 || (g.kind == 0 ? g.nins == g.K : g.nins == 0);
+    if (g.kind == 3 || g.kind == 5) return -1;
+    const bool full = g.kind == 2 || g.kind == 4 || (g.kind == 0 ? g.nins == g.K : g.nins == 0);
     return full ? SV_COST_TILED_RECORD : SV_COST_TILED_RECORD_PART;
 }
 

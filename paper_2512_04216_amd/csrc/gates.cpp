@@ -482,6 +482,62 @@ void pass_records(const sv_op *sops, const std::vector<TiledOp> &ops, const Pass
             recs.push_back(g);
         }
     };
+    // A run of uncontrolled diagonal ops as one parity run: every diagonal
+    // factor on <= 2 qubits is exp(i a(m)) with a(m) = c + w0 b0 + w1 b1 +
+    // w01 (b0 xor b1) (four values, four coefficients), so the run's angle is
+    // a constant plus a weighted sum of parities of bit masks (RZZ(g): one mask
+    // of weight g; RZ(t): one of weight t). Equal masks are merged; when every
+    // weight is the same (a QAOA cost layer) the kernel counts parities and
+    // looks the phase up in a per-tile table instead of one sincos per
+    // amplitude.
+    constexpr int kMaxParityTable = 127;
+    auto emit_parity_run = [&](const int *idx, int cnt) {
+        std::map<uint64_t, double> wsum;
+        double c = 0.0;
+        for (int r = 0; r < cnt; ++r) {
+            const GateDesc &d = ops[idx[r]].d;
+            double a[4];
+            const int k = d.diag.k;
+            for (int m = 0; m < 1 << k; ++m) a[m] = std::atan2(d.diag.d[2 * m + 1], d.diag.d[2 * m]);
+            const uint64_t b0 = 1ull << d.diag.targets[0];
+            if (k == 1) {
+                c += a[0];
+                wsum[b0] += a[1] - a[0];
+            } else {
+                const uint64_t b1 = 1ull << d.diag.targets[1];
+                const double w01 = 0.5 * (a[1] + a[2] - a[3] - a[0]);
+                c += a[0];
+                wsum[b0] += a[1] - a[0] - w01;
+                wsum[b1] += a[2] - a[0] - w01;
+                wsum[b0 | b1] += w01;
+            }
+        }
+        std::vector<std::pair<uint64_t, double>> terms;
+        for (auto &kv : wsum)
+            if (kv.second != 0.0) terms.push_back(kv);
+        svk::TileGate h;
+        h.kind = 4;
+        h.K = (int)terms.size();
+        h.u[0] = c;
+        bool same = !terms.empty() && (int)terms.size() <= kMaxParityTable;
+        for (auto &t : terms) same = same && t.second == terms[0].second;
+        h.pm = same ? 1u : 0u;
+        h.u[1] = terms.empty() ? 0.0 : terms[0].second;
+        recs.push_back(h);
+        for (auto &t : terms) {
+            svk::TileGate g;
+            g.kind = 5;
+            g.pm = compress(t.first & Q);
+            g.gm = t.first & ~Q;
+            g.u[0] = t.second;
+            recs.push_back(g);
+        }
+    };
+    auto uncontrolled = [&](const int *idx, int cnt) {
+        for (int r = 0; r < cnt; ++r)
+            if (ops[idx[r]].d.diag.cmask != 0) return false;
+        return true;
+    };
     // Phase runs take general diagonal gates (every amplitude gets a factor, as
     // RZ and RZZ) with unit-modulus factors; a phase on one pattern (CP, CZ, S,
     // T) touches only its members and stays a gate of its own.
@@ -558,7 +614,8 @@ void pass_records(const sv_op *sops, const std::vector<TiledOp> &ops, const Pass
     for (int i = 0; i < nl;) {
         const int rl = run_len(i);
         if (rl >= kMinRun) {
-            emit_run(&L[i], rl);
+            if (uncontrolled(&L[i], rl)) emit_parity_run(&L[i], rl);
+            else emit_run(&L[i], rl);
             i += rl;
             continue;
         }

@@ -24,6 +24,7 @@ using namespace svd;
 namespace {
 
 constexpr int kTT = 1024;   // threads per tile workgroup (16 wavefronts)
+constexpr int kTableBytes = 4096;   // phase table of a parity run: at most 2*127+1 complex128
 
 // Local index of base member e: zeros inserted at the gate's fixed local bits
 // (ascending), then their values.
@@ -54,7 +55,9 @@ __global__ __launch_bounds__(kTT) void k_tiled(svk::TileArgs a, const svk::TileG
     extern __shared__ __align__(16) unsigned char smem[];
     Cx<T> *lds = reinterpret_cast<Cx<T> *>(smem);
     u4 *ldsv = reinterpret_cast<u4 *>(smem);
-    uint64_t *hoff = reinterpret_cast<uint64_t *>(smem + (sizeof(Cx<T>) << MB));
+    // LDS: the tile, the phase table of parity runs, the high-bit offsets
+    Cx<T> *ptab = reinterpret_cast<Cx<T> *>(smem + (sizeof(Cx<T>) << MB));
+    uint64_t *hoff = reinterpret_cast<uint64_t *>(smem + (sizeof(Cx<T>) << MB) + kTableBytes);
     const uint64_t tile = xcd_block();
     if (tile >= a.ntiles) return;   // the whole workgroup leaves together
     const int tid = threadIdx.x;
@@ -162,6 +165,65 @@ __global__ __launch_bounds__(kTT) void k_tiled(svk::TileArgs a, const svk::TileG
                 lds[j] = cmul(Cx<T>{(T)cs, (T)sn}, lds[j]);
             }
             gi += nt;
+        } else if (g.kind == 4) {
+            // Parity run: angle(j) = c + sum_t w_t parity(j & mask_t) over the
+            // global index. A term's bits outside the tile give it a fixed parity
+            // f for the whole tile, and w (f xor p) = w f + (1 - 2f) w p: the
+            // constant goes into c, the sign into the term.
+            const int P = g.K;
+            const svk::TileGate *terms = gates + a.gate0 + gi + 1;
+            double c = g.u[0];
+            for (int t = 0; t < P; ++t)
+                if (__builtin_popcountll(base & terms[t].gm) & 1) c += terms[t].u[0];
+            constexpr int APT = (1 << MB) / kTT;
+            const uint32_t size = 1u << mb;
+            if (g.pm) {
+                // one common weight w: count the signed parities k in [-P, P] and
+                // take exp(i (c + w k)) from a table filled once per tile
+                const double w = g.u[1];
+                if (tid <= 2 * P) {
+                    double sn, cs;
+                    sincos(c + w * (double)(tid - P), &sn, &cs);
+                    ptab[tid] = Cx<T>{(T)cs, (T)sn};
+                }
+                __syncthreads();
+                // terms outer, this thread's amplitudes inner: each term's mask and
+                // sign are read once per thread
+                int kq[APT];
+#pragma unroll
+                for (int q = 0; q < APT; ++q) kq[q] = P;
+                for (int t = 0; t < P; ++t) {
+                    const uint32_t lm = terms[t].pm;
+                    if (lm == 0) continue;
+                    const bool neg = __builtin_popcountll(base & terms[t].gm) & 1;
+#pragma unroll
+                    for (int q = 0; q < APT; ++q) {
+                        const int par = __builtin_popcount((uint32_t)(tid + q * kTT) & lm) & 1;
+                        kq[q] += neg ? -par : par;
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < APT; ++q) {
+                    const uint32_t j = tid + q * kTT;
+                    if (j < size) lds[j] = cmul(ptab[kq[q]], lds[j]);
+                }
+            } else {
+#pragma unroll 1
+                for (int q = 0; q < APT; ++q) {
+                    const uint32_t j = tid + q * kTT;
+                    if (j >= size) break;
+                    double ang = c;
+                    for (int t = 0; t < P; ++t) {
+                        const double wt = (__builtin_popcountll(base & terms[t].gm) & 1) ? -terms[t].u[0]
+                                                                                       : terms[t].u[0];
+                        if (__builtin_popcount(j & terms[t].pm) & 1) ang += wt;
+                    }
+                    double sn, cs;
+                    sincos(ang, &sn, &cs);
+                    lds[j] = cmul(Cx<T>{(T)cs, (T)sn}, lds[j]);
+                }
+            }
+            gi += P;
         } else {
             // diagonal: factor index from the target bits, the ones outside the tile fixed
             uint32_t mfix = 0;
@@ -186,7 +248,7 @@ __global__ __launch_bounds__(kTT) void k_tiled(svk::TileArgs a, const svk::TileG
 
 template <typename T, int MB>
 constexpr size_t tile_lds_bytes(int lb_full) {
-    return (sizeof(Cx<T>) << MB) + (sizeof(uint64_t) << (MB - lb_full));
+    return (sizeof(Cx<T>) << MB) + kTableBytes + (sizeof(uint64_t) << (MB - lb_full));
 }
 
 template <typename T, int MB>

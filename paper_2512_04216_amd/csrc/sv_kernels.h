@@ -94,7 +94,10 @@ inline int tile_bits(int is_c64) { return is_c64 ? 14 : 13; }   // 128 KiB of LD
 // record applies where (j & pm) == pv and (global index & gm) == gv, with angle
 // u[m], m = its target bits.
 struct TileGate {
-    int32_t kind = 0;       // 0: group (K flip vectors), 1: diagonal, 2: phase run, 3: run term
+    int32_t kind = 0;       // 0: group (K flip vectors), 1: diagonal, 2: phase run, 3: run term,
+                            // 4: parity run (K parity terms follow; u[0] constant angle, u[1] the
+                            //    common weight when pm = 1), 5: parity term (pm local mask, gm mask of
+                            //    the bits outside the tile, u[0] weight)
     int32_t K = 0;          // group: flip vectors (0..2); diagonal, run term: targets (0..2); run: terms
     int32_t nins = 0;       // local bits fixed by the gate, ascending: zeros inserted when
     int32_t ins[7] = {0};   //   enumerating its base members
