@@ -306,7 +306,11 @@ sv_status sv_pblock_destroy(sv_pblock p);
  * classical bits: SV_OP_COND gates test it, SV_OP_MEASURE writes it. The op
  * list is validated before anything runs; an error while running (SV_E_OOM,
  * a block beyond the size limit) leaves the state partly updated and drops
- * the gates still queued. Synchronous. */
+ * the gates still queued. Block states live in the context's arena and run on
+ * its stream; merges grow a block's buffer in place where the arena allows,
+ * splits shrink it in place, and the memory they release is reused in that
+ * stream's order (work on other streams must not allocate from the same
+ * context while a p-block call runs). Synchronous. */
 sv_status sv_pblock_run(sv_pblock p, const sv_op *ops, int nops, int fuse_k, uint64_t seed,
                         uint64_t *clbits);
 

@@ -24,73 +24,6 @@ sv_status hip_fail(hipError_t e, const char *what) {
 }
 
 // ---- arena --------------------------------------------------------------------
-void Arena::init(char *base, uint64_t size) {
-    std::lock_guard<std::mutex> g(mu_);
-    base_ = base;
-    size_ = size;
-    free_.clear();
-    used_.clear();
-    if (size) free_[0] = size;
-}
-
-void *Arena::alloc(uint64_t bytes, uint64_t align) {
-    std::lock_guard<std::mutex> g(mu_);
-    if (bytes == 0) bytes = 1;
-    bytes = (bytes + 255) & ~255ull;
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-        const uint64_t off = it->first, len = it->second;
-        const uint64_t a = (off + align - 1) / align * align;
-        if (a + bytes > off + len) continue;
-        free_.erase(it);
-        if (a > off) free_[off] = a - off;
-        if (a + bytes < off + len) free_[a + bytes] = off + len - (a + bytes);
-        used_[a] = bytes;
-        return base_ + a;
-    }
-    return nullptr;
-}
-
-void Arena::free(void *p) {
-    if (!p) return;
-    std::lock_guard<std::mutex> g(mu_);
-    const uint64_t off = (uint64_t)((char *)p - base_);
-    auto u = used_.find(off);
-    if (u == used_.end()) return;
-    uint64_t start = off, len = u->second;
-    used_.erase(u);
-    auto nx = free_.lower_bound(start);
-    if (nx != free_.end() && nx->first == start + len) {
-        len += nx->second;
-        free_.erase(nx);
-    }
-    auto pv = free_.lower_bound(start);
-    if (pv != free_.begin()) {
-        --pv;
-        if (pv->first + pv->second == start) {
-            start = pv->first;
-            len += pv->second;
-            free_.erase(pv);
-        }
-    }
-    free_[start] = len;
-}
-
-uint64_t Arena::free_bytes() const {
-    std::lock_guard<std::mutex> g(mu_);
-    uint64_t t = 0;
-    for (auto &f : free_) t += f.second;
-    return t;
-}
-
-uint64_t Arena::largest_free() const {
-    std::lock_guard<std::mutex> g(mu_);
-    uint64_t t = 0;
-    for (auto &f : free_) t = std::max(t, f.second);
-    return t;
-}
-
-bool Arena::contains(const void *p) const { return (const char *)p >= base_ && (const char *)p < base_ + size_; }
-
 // ---- tracing ------------------------------------------------------------------
 hipEvent_t Tracer::get_event() {
     if (!pool.empty()) {
@@ -161,7 +94,7 @@ int StagePool::acquire(Arena &arena, uint64_t bytes) {
     while (sz < bytes) sz <<= 1;
     StageBuf b;
     b.bytes = sz;
-    b.dev = (char *)arena.alloc(sz);
+    b.dev = (char *)arena.alloc_high(sz);   // small, long-lived: away from growing states
     if (!b.dev) return -1;
     if (hipHostMalloc((void **)&b.host, sz, hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess) {
@@ -448,9 +381,9 @@ sv_status sv_create(sv_ctx c, int n, sv_dtype dt, sv_state *out) {
 
 }  // extern "C"
 
-sv_status svh::state_create(sv_ctx c, int n, sv_dtype dt, hipStream_t stream, sv_state *out) {
+sv_status svh::state_create(sv_ctx c, int n, sv_dtype dt, hipStream_t stream, sv_state *out, bool high) {
     sv_state st = nullptr;
-    sv_status r = state_alloc(c, n, dt, stream, &st);
+    sv_status r = state_alloc(c, n, dt, stream, &st, high);
     if (r) return r;
     r = sv_reset(st, 0);
     if (r != SV_OK) {
@@ -461,7 +394,7 @@ sv_status svh::state_create(sv_ctx c, int n, sv_dtype dt, hipStream_t stream, sv
     return SV_OK;
 }
 
-sv_status svh::state_alloc(sv_ctx c, int n, sv_dtype dt, hipStream_t stream, sv_state *out) {
+sv_status svh::state_alloc(sv_ctx c, int n, sv_dtype dt, hipStream_t stream, sv_state *out, bool high) {
     if (dt != SV_C64 && dt != SV_C128) return fail(SV_E_INVALID, "dtype must be SV_C64 or SV_C128");
     const int nmax = dt == SV_C64 ? SV_MAX_QUBITS_C64 : SV_MAX_QUBITS_C128;
     if (n < 1 || n > nmax) return fail(SV_E_INVALID, "n out of range [1, " + std::to_string(nmax) + "]");
@@ -471,12 +404,14 @@ sv_status svh::state_alloc(sv_ctx c, int n, sv_dtype dt, hipStream_t stream, sv_
     st->dtype = dt;
     st->bytes = state_bytes(n, dt);
     st->ws_bytes = svk::measure_workspace_bytes(n);
-    st->psi = c->arena.alloc(st->bytes, 1 << 16);
+    st->psi = high ? c->arena.alloc_high(st->bytes, 1 << 16) : c->arena.alloc(st->bytes, 1 << 16);
     if (!st->psi) {
         delete st;
         return fail(SV_E_OOM, "arena cannot hold a state of " + std::to_string(n) + " qubits");
     }
-    st->ws = c->arena.alloc(st->ws_bytes);
+    // workspaces from the top of the arena: they never sit right after a
+    // state that may later grow in place
+    st->ws = c->arena.alloc_high(st->ws_bytes);
     if (!st->ws) {
         c->arena.free(st->psi);
         delete st;

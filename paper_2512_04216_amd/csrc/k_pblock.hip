@@ -3,9 +3,10 @@
 // A p-block state keeps one state vector per group of qubits that have
 // interacted (Sec. II, p-block simulation): a gate across groups merges their
 // states into their tensor product, and a measured qubit leaves its group.
-//   k_kron:  out[i] = A[A's bits of i] * B[B's bits of i] (merge of two groups)
-//   k_split: out[i'] = c * psi[i' with bit j set to m] (a measured qubit leaves)
-// Both stream their output once; every thread writes whole 16-byte slices.
+//   k_kron:       out[i] = A[A's bits of i] * B[B's bits of i] (merge of two groups)
+//   k_kron_top:   the same with A's qubits above B's, writing into B's grown buffer
+//   k_split_move: psi[i'] = c * psi[i' with bit j set to m], in place (a measured
+//                 qubit leaves; the upper half of the buffer is given back)
 #include "sv_device.h"
 #include "sv_kernels.h"
 
@@ -52,15 +53,34 @@ __global__ __launch_bounds__(kB) void k_kron(const Cx<T> *__restrict__ A, KronPo
     }
 }
 
+// Merge with all of A's qubits above B's: out[ib + (ka << b)] = A[ka] B[ib].
+// One item per amplitude of B writes all 2^a outputs after reading it, and
+// only the output ib lies inside B's range, so out may be B's own (grown)
+// buffer.
 template <typename T>
-__global__ __launch_bounds__(kB) void k_split(const Cx<T> *__restrict__ psi, int j, int m, double c, uint64_t nout,
-                                              Cx<T> *__restrict__ out) {
+__global__ __launch_bounds__(kB) void k_kron_top(const Cx<T> *__restrict__ A, int a, const Cx<T> *B, int b,
+                                                 Cx<T> *out) {
+    const uint64_t stride = grid_blocks() * kB;
+    const uint64_t nb = 1ull << b;
+    for (uint64_t ib = block_linear() * kB + threadIdx.x; ib < nb; ib += stride) {
+        const Cx<T> v = B[ib];
+        for (int ka = 0; ka < (1 << a); ++ka) out[ib + ((uint64_t)ka << b)] = mul(A[ka], v);
+    }
+}
+
+// In-place split, one batch: out block k (2^j amplitudes) <- c * in block
+// 2k + m, for the blocks [k0, k1) of the batch. Batches run in the order
+// {0}, {1}, [2, 4), [4, 8), ...: a batch reads only blocks at or above 2 k0 + m
+// and writes below 2 k0, so no block is overwritten before it has been read.
+template <typename T>
+__global__ __launch_bounds__(kB) void k_split_move(Cx<T> *psi, int j, int m, double c, uint64_t k0, uint64_t k1) {
     const uint64_t stride = grid_blocks() * kB;
     const uint64_t lo = (1ull << j) - 1ull;
-    for (uint64_t i = block_linear() * kB + threadIdx.x; i < nout; i += stride) {
-        const uint64_t src = ((i & ~lo) << 1) | ((uint64_t)m << j) | (i & lo);
+    const uint64_t i0 = k0 << j, i1 = k1 << j;
+    for (uint64_t i = i0 + block_linear() * kB + threadIdx.x; i < i1; i += stride) {
+        const uint64_t src = ((((i >> j) << 1) | (uint64_t)m) << j) | (i & lo);
         const Cx<T> v = psi[src];
-        out[i] = Cx<T>{(T)(v.re * c), (T)(v.im * c)};
+        psi[i] = Cx<T>{(T)(v.re * c), (T)(v.im * c)};
     }
 }
 
@@ -129,15 +149,30 @@ hipError_t launch_kron(const void *A, const KronPos &pos, const void *B, int b, 
     return hipGetLastError();
 }
 
-hipError_t launch_split(const void *psi, int n, int j, int m, double c, void *out, int is_c64, hipStream_t s) {
-    const uint64_t nout = 1ull << (n - 1);
-    const dim3 g((unsigned)blocks_for(nout));
+hipError_t launch_kron_top(const void *A, int a, const void *B, int b, void *out, int is_c64, hipStream_t s) {
+    const dim3 g((unsigned)blocks_for(1ull << b));
     if (is_c64)
-        hipLaunchKernelGGL(k_split<float>, g, dim3(kB), 0, s, (const Cx<float> *)psi, j, m, c, nout, (Cx<float> *)out);
+        hipLaunchKernelGGL(k_kron_top<float>, g, dim3(kB), 0, s, (const Cx<float> *)A, a, (const Cx<float> *)B, b,
+                           (Cx<float> *)out);
     else
-        hipLaunchKernelGGL(k_split<double>, g, dim3(kB), 0, s, (const Cx<double> *)psi, j, m, c, nout,
+        hipLaunchKernelGGL(k_kron_top<double>, g, dim3(kB), 0, s, (const Cx<double> *)A, a, (const Cx<double> *)B, b,
                            (Cx<double> *)out);
     return hipGetLastError();
+}
+
+hipError_t launch_split_inplace(void *psi, int n, int j, int m, double c, int is_c64, hipStream_t s) {
+    const uint64_t nblk = 1ull << (n - 1 - j);   // blocks of 2^j amplitudes in the result
+    for (uint64_t k0 = 0, k1 = 1; k0 < nblk; k0 = k1, k1 = std::min<uint64_t>(nblk, k1 ? 2 * k1 : 1)) {
+        const dim3 g((unsigned)blocks_for((k1 - k0) << j));
+        if (is_c64)
+            hipLaunchKernelGGL(k_split_move<float>, g, dim3(kB), 0, s, (Cx<float> *)psi, j, m, c, k0, k1);
+        else
+            hipLaunchKernelGGL(k_split_move<double>, g, dim3(kB), 0, s, (Cx<double> *)psi, j, m, c, k0, k1);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        if (k1 == nblk) break;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_gather_mul(const void *psi, int is_c64, const BlockMap &m, const uint64_t *gidx_dev, int64_t count,

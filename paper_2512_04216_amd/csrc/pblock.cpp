@@ -3,13 +3,18 @@
 //
 // The state of n qubits is a tensor product of blocks; each block is an
 // ordinary device state (sv_state) of the qubits that have interacted. A gate
-// spanning several blocks merges them (k_kron); a measured or reset qubit
-// leaves its block (k_split projects, rescales and drops its bit in one pass),
-// so communication qubits return to blocks of their own as soon as a protocol
-// measures them. A block's index bits hold its qubits in ascending order, so
-// its amplitudes, CDF and draws do not depend on the order of the merges.
-// Gates on one block queue up and run as one sv_run call (per gate, fused or
-// tiled) when the block is next merged, measured or read.
+// spanning several blocks merges them (k_kron; when the smaller block's
+// qubits all lie above the larger one's, the larger block's buffer grows in
+// place and k_kron_top writes the product into it); a measured or reset
+// qubit leaves its block (k_split_move projects, rescales and drops its bit in
+// place, and the upper half of the buffer goes back to the arena), so
+// communication qubits return to blocks of their own as soon as a protocol
+// measures them, without a second copy of the block. A block's index bits
+// hold its qubits in ascending order, so its amplitudes, CDF and draws do not
+// depend on the order of the merges. Small blocks live at the top of the
+// arena, leaving the bottom for large blocks to grow. Gates on one block queue
+// up and run as one sv_run call (per gate, fused or tiled) when the block is
+// next merged, measured or read.
 #include "sv_host.h"
 
 #include <algorithm>
@@ -19,6 +24,8 @@
 using namespace svh;
 
 namespace {
+
+constexpr int kSmallBlock = 16;   // qubits of the blocks placed at the top of the arena
 
 struct PBlk {
     sv_state st = nullptr;
@@ -79,7 +86,45 @@ void remove_block(sv_pblock p, PBlk *b) {
     delete b;
 }
 
-// Tensor product of two blocks (both flushed); A and B are freed.
+// B grows in place into A (x) B: A's qubits all lie above B's, A is small
+// (its 2^a amplitudes per item), and the arena extent after B's amplitudes is
+// free. False (nothing changed) when any of that fails.
+bool merge_in_place(sv_pblock p, PBlk *A, PBlk *B) {
+    const int a = (int)A->q.size(), b = (int)B->q.size();
+    if (a > 4 || A->q.front() < B->q.back()) return false;
+    sv_ctx c = p->ctx;
+    sv_state st = B->st;
+    void *ws = c->arena.alloc_high(svk::measure_workspace_bytes(a + b));
+    if (!ws) return false;
+    const uint64_t nbytes = state_bytes(a + b, p->dt);
+    if (!c->arena.grow(st->psi, nbytes)) {
+        c->arena.free(ws);
+        return false;
+    }
+    hipError_t e;
+    {
+        TraceScope ts(&c->tracer, st->stream, "kron", (double)nbytes + A->st->bytes + st->bytes);
+        e = svk::launch_kron_top(A->st->psi, a, st->psi, b, st->psi, st->is_c64(), st->stream);
+    }
+    if (e != hipSuccess) {   // the launch did not start: undo the growth
+        c->arena.shrink(st->psi, st->bytes);
+        c->arena.free(ws);
+        return false;
+    }
+    p->cur += nbytes - st->bytes;
+    p->peak = std::max(p->peak, p->cur);
+    c->arena.free(st->ws);
+    st->ws = ws;
+    st->ws_bytes = svk::measure_workspace_bytes(a + b);
+    st->n = a + b;
+    st->bytes = nbytes;
+    st->sweeps_since_renorm = 0;
+    B->q.insert(B->q.end(), A->q.begin(), A->q.end());
+    return true;
+}
+
+// Tensor product of two blocks (both flushed); A and B are freed (or B grows
+// into the product).
 sv_status merge(sv_pblock p, PBlk *A, PBlk *B, PBlk **out) {
     sv_status r = flush(p, A);
     if (!r) r = flush(p, B);
@@ -90,8 +135,16 @@ sv_status merge(sv_pblock p, PBlk *A, PBlk *B, PBlk **out) {
     if (a + b > nmax)
         return fail(SV_E_INVALID, "entangled block of " + std::to_string(a + b) + " qubits exceeds " +
                                       std::to_string(nmax));
+    if (merge_in_place(p, A, B)) {
+        remove_block(p, A);
+        reindex(p, B);
+        *out = B;
+        return SV_OK;
+    }
+    // small blocks come from the top of the arena, so that the bottom keeps
+    // room for large blocks to grow into
     sv_state st = nullptr;
-    r = state_alloc(p->ctx, a + b, p->dt, p->ctx->stream, &st);
+    r = state_alloc(p->ctx, a + b, p->dt, p->ctx->stream, &st, a + b <= kSmallBlock);
     if (r) return r;
     // block qubits stay in ascending order: A's qubits take their places among B's
     std::vector<int> mq(A->q);
@@ -139,41 +192,37 @@ sv_status measure(sv_pblock p, int q, bool reset, double u, int *m_out) {
     *m_out = m;
     if (B->q.size() == 1) return collapse(B->st, 0, m, pm, reset);
     // the projected state is |m>_q (x) rest: the rest keeps the amplitudes
-    // with bit j = m, scaled by 1/sqrt(pm); q gets a block of its own
+    // with bit j = m, scaled by 1/sqrt(pm), compacted in place into the lower
+    // half of the block, whose upper half goes back to the arena; q gets a
+    // block of its own
     const int nb = (int)B->q.size();
-    sv_state rest = nullptr, one = nullptr;
-    r = state_alloc(p->ctx, nb - 1, p->dt, p->ctx->stream, &rest);
+    sv_state one = nullptr;
+    r = state_create(p->ctx, 1, p->dt, p->ctx->stream, &one, true);
     if (r) return r;
-    r = state_create(p->ctx, 1, p->dt, p->ctx->stream, &one);
-    if (r) {
-        hipStreamSynchronize(rest->stream);
-        state_release(rest);
-        return r;
-    }
+    sv_state st = B->st;
     hipError_t e;
     {
-        TraceScope ts(&p->ctx->tracer, rest->stream, "split", 2.0 * rest->bytes);
-        e = svk::launch_split(B->st->psi, nb, j, m, 1.0 / std::sqrt(pm), rest->psi, rest->is_c64(), rest->stream);
+        TraceScope ts(&p->ctx->tracer, st->stream, "split", (double)st->bytes);
+        e = svk::launch_split_inplace(st->psi, nb, j, m, 1.0 / std::sqrt(pm), st->is_c64(), st->stream);
     }
     if (e == hipSuccess && !reset && m) e = svk::launch_init(one->psi, 1, one->is_c64(), 1, one->stream);
     if (e != hipSuccess) {
-        hipStreamSynchronize(rest->stream);
-        state_release(rest);
+        hipStreamSynchronize(st->stream);
         state_release(one);
         return hip_fail(e, "block split");
     }
-    hold(p, rest);
+    const uint64_t half = state_bytes(nb - 1, p->dt);
+    p->ctx->arena.shrink(st->psi, half);   // later users of the tail run on the same stream
+    p->cur -= st->bytes - half;
+    st->n = nb - 1;
+    st->bytes = half;
+    B->q.erase(B->q.begin() + j);
     hold(p, one);
-    PBlk *R = new PBlk(), *Q = new PBlk();
-    R->st = rest;
-    R->q = B->q;
-    R->q.erase(R->q.begin() + j);
+    PBlk *Q = new PBlk();
     Q->st = one;
     Q->q = {q};
-    remove_block(p, B);
-    p->blocks.push_back(R);
     p->blocks.push_back(Q);
-    reindex(p, R);
+    reindex(p, B);
     reindex(p, Q);
     return SV_OK;
 }
@@ -239,7 +288,7 @@ sv_status sv_pblock_create(sv_ctx c, int n, sv_dtype dt, sv_pblock *out) {
     }
     for (int q = 0; q < n && !r; ++q) {
         PBlk *b = new PBlk();
-        r = state_create(c, 1, dt, c->stream, &b->st);
+        r = state_create(c, 1, dt, c->stream, &b->st, true);
         if (r) {
             delete b;
             break;

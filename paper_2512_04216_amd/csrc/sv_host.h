@@ -3,6 +3,7 @@
 
 #include "../../include/sv.h"
 #include "sv_kernels.h"
+#include "arena.h"
 
 #include <hip/hip_runtime_api.h>
 
@@ -24,26 +25,6 @@ sv_status hip_fail(hipError_t e, const char *what);
         hipError_t _e = (call);                      \
         if (_e != hipSuccess) return svh::hip_fail(_e, #call); \
     } while (0)
-
-// ---- arena: first-fit sub-allocator over one device block -------------------
-class Arena {
-  public:
-    void init(char *base, uint64_t size);
-    // returns nullptr when no extent fits
-    void *alloc(uint64_t bytes, uint64_t align = 256);
-    void free(void *p);
-    uint64_t free_bytes() const;
-    uint64_t largest_free() const;
-    uint64_t size() const { return size_; }
-    bool contains(const void *p) const;
-
-  private:
-    mutable std::mutex mu_;
-    char *base_ = nullptr;
-    uint64_t size_ = 0;
-    std::map<uint64_t, uint64_t> free_;   // offset -> length
-    std::map<uint64_t, uint64_t> used_;   // offset -> length
-};
 
 // ---- tracing ----------------------------------------------------------------
 struct TraceAgg {
@@ -214,10 +195,12 @@ sv_status norm_device(sv_state st);   // leaves ||psi||^2 at norm2_dev_ptr
 sv_status renorm(sv_state st);        // psi <- psi / ||psi|| on the state's stream
 // free a state without waiting for its stream (its work must be complete)
 sv_status state_release(sv_state st);
-// allocate a state on a given stream (sv_create uses the context's stream)
-sv_status state_create(sv_ctx c, int n, sv_dtype dt, hipStream_t stream, sv_state *out);
+// allocate a state on a given stream (sv_create uses the context's stream);
+// `high` places its amplitudes at the top of the arena (small long-lived
+// states), the measurement workspace always goes there
+sv_status state_create(sv_ctx c, int n, sv_dtype dt, hipStream_t stream, sv_state *out, bool high = false);
 // the same without initialising the amplitudes (the caller writes every one)
-sv_status state_alloc(sv_ctx c, int n, sv_dtype dt, hipStream_t stream, sv_state *out);
+sv_status state_alloc(sv_ctx c, int n, sv_dtype dt, hipStream_t stream, sv_state *out, bool high = false);
 
 // ---- mid-circuit measurement ----------------------------------------------
 // U01(seed, s): the sampler's generator (SplitMix64 at counter s, 53-bit uniform)

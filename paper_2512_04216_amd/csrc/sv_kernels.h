@@ -206,8 +206,12 @@ struct KronPos {
 // A's index, its other bits in order form B's index.
 hipError_t launch_kron(const void *A, const KronPos &pos, const void *B, int b, void *out, int is_c64,
                        hipStream_t s);
-// out (n-1 qubits) <- c * psi restricted to bit j == m, bit j removed.
-hipError_t launch_split(const void *psi, int n, int j, int m, double c, void *out, int is_c64, hipStream_t s);
+// out (2^(a+b)) <- A (x) B with A's a qubits above all of B's: out[ib + 2^b ka]
+// = A[ka] B[ib]; out may be B's own buffer grown to 2^(a+b) amplitudes.
+hipError_t launch_kron_top(const void *A, int a, const void *B, int b, void *out, int is_c64, hipStream_t s);
+// psi (n qubits) <- its first 2^(n-1) amplitudes = c * psi restricted to bit
+// j == m with bit j removed, in place (a few ordered launches).
+hipError_t launch_split_inplace(void *psi, int n, int j, int m, double c, int is_c64, hipStream_t s);
 // acc[i] (FP64 complex) <- (first ? 1 : acc[i]) * psi[block bits of global index i]
 hipError_t launch_gather_mul(const void *psi, int is_c64, const BlockMap &m, const uint64_t *gidx_dev, int64_t count,
                              double *acc_dev, int first, hipStream_t s);
