@@ -68,6 +68,41 @@ bool Arena::grow(void *p, uint64_t bytes) {
     return true;
 }
 
+void *Arena::grow_around(void *p, uint64_t units, uint64_t unit, uint64_t align, uint64_t *k) {
+    std::lock_guard<std::mutex> g(mu_);
+    const uint64_t off = (uint64_t)((char *)p - base_);
+    auto u = used_.find(off);
+    if (u == used_.end() || u->second != unit || units == 0) return nullptr;
+    auto nx = free_.find(off + unit);
+    const uint64_t after = nx == free_.end() ? 0 : nx->second;
+    auto pv = free_.lower_bound(off);
+    uint64_t before = 0, bstart = off;
+    if (pv != free_.begin()) {
+        --pv;
+        if (pv->first + pv->second == off) {
+            before = pv->second;
+            bstart = pv->first;
+        }
+    }
+    for (uint64_t kk = 0; kk < units; ++kk) {
+        const uint64_t lo = kk * unit, hi = (units - 1 - kk) * unit;
+        if (lo > before || hi > after || (off - lo) % align != 0) continue;
+        if (lo) {
+            free_.erase(bstart);
+            if (before > lo) free_[bstart] = before - lo;
+        }
+        if (hi) {
+            free_.erase(off + unit);
+            if (after > hi) free_[off + unit + hi] = after - hi;
+        }
+        used_.erase(u);
+        used_[off - lo] = units * unit;
+        *k = kk;
+        return base_ + (off - lo);
+    }
+    return nullptr;
+}
+
 void Arena::shrink(void *p, uint64_t bytes) {
     std::lock_guard<std::mutex> g(mu_);
     const uint64_t off = (uint64_t)((char *)p - base_);

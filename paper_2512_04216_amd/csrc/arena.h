@@ -19,6 +19,13 @@ class Arena {
     // extend the allocation at p in place to `bytes` when the free extent
     // right after it is large enough; false (nothing changed) otherwise
     bool grow(void *p, uint64_t bytes);
+    // extend the allocation at p (currently `unit` bytes) to units * unit
+    // bytes around itself: the old bytes end up at unit position *k of the new
+    // allocation, with k * unit taken from the free extent just below p and the
+    // rest from the one just above (the lowest k that fits and keeps the new
+    // start aligned). Returns the new start, nullptr (nothing changed) if no k
+    // fits.
+    void *grow_around(void *p, uint64_t units, uint64_t unit, uint64_t align, uint64_t *k);
     // give back the part of the allocation at p beyond `bytes`
     void shrink(void *p, uint64_t bytes);
     void free(void *p);

@@ -54,9 +54,10 @@ __global__ __launch_bounds__(kB) void k_kron(const Cx<T> *__restrict__ A, KronPo
 }
 
 // Merge with all of A's qubits above B's: out[ib + (ka << b)] = A[ka] B[ib].
-// One item per amplitude of B writes all 2^a outputs after reading it, and
-// only the output ib lies inside B's range, so out may be B's own (grown)
-// buffer.
+// One item per amplitude of B writes all 2^a outputs after reading it, and B
+// may be copy k of out itself (B's buffer grown around it): then the only
+// output inside B's range that item ib writes is out[ib + (k << b)], the value
+// it has just read.
 template <typename T>
 __global__ __launch_bounds__(kB) void k_kron_top(const Cx<T> *__restrict__ A, int a, const Cx<T> *B, int b,
                                                  Cx<T> *out) {

@@ -87,29 +87,36 @@ void remove_block(sv_pblock p, PBlk *b) {
 }
 
 // B grows in place into A (x) B: A's qubits all lie above B's, A is small
-// (its 2^a amplitudes per item), and the arena extent after B's amplitudes is
-// free. False (nothing changed) when any of that fails.
-bool merge_in_place(sv_pblock p, PBlk *A, PBlk *B) {
+// (its 2^a amplitudes per item), and the free arena extents just below and
+// above B's amplitudes hold the other 2^a - 1 copies of B's size between them
+// (B's old amplitudes then sit at copy k of the product, which is where
+// k_kron_top reads them). Returns 0 when not applicable (nothing changed),
+// 1 when done, -1 when the launch failed (the state is then unusable).
+int merge_in_place(sv_pblock p, PBlk *A, PBlk *B) {
     const int a = (int)A->q.size(), b = (int)B->q.size();
-    if (a > 4 || A->q.front() < B->q.back()) return false;
+    if (a > 4 || A->q.front() < B->q.back()) return 0;
     sv_ctx c = p->ctx;
     sv_state st = B->st;
+    if (st->bytes % 256 != 0) return 0;   // the arena holds B in whole 256-byte units
     void *ws = c->arena.alloc_high(svk::measure_workspace_bytes(a + b));
-    if (!ws) return false;
+    if (!ws) return 0;
     const uint64_t nbytes = state_bytes(a + b, p->dt);
-    if (!c->arena.grow(st->psi, nbytes)) {
+    uint64_t k = 0;
+    char *base = (char *)c->arena.grow_around(st->psi, 1ull << a, st->bytes, 1ull << 16, &k);
+    if (!base) {
         c->arena.free(ws);
-        return false;
+        return 0;
     }
     hipError_t e;
     {
         TraceScope ts(&c->tracer, st->stream, "kron", (double)nbytes + A->st->bytes + st->bytes);
-        e = svk::launch_kron_top(A->st->psi, a, st->psi, b, st->psi, st->is_c64(), st->stream);
+        e = svk::launch_kron_top(A->st->psi, a, base + k * st->bytes, b, base, st->is_c64(), st->stream);
     }
-    if (e != hipSuccess) {   // the launch did not start: undo the growth
-        c->arena.shrink(st->psi, st->bytes);
+    st->psi = base;   // the grown extent, whatever happened
+    if (e != hipSuccess) {
         c->arena.free(ws);
-        return false;
+        hip_fail(e, "block merge");
+        return -1;
     }
     p->cur += nbytes - st->bytes;
     p->peak = std::max(p->peak, p->cur);
@@ -120,7 +127,7 @@ bool merge_in_place(sv_pblock p, PBlk *A, PBlk *B) {
     st->bytes = nbytes;
     st->sweeps_since_renorm = 0;
     B->q.insert(B->q.end(), A->q.begin(), A->q.end());
-    return true;
+    return 1;
 }
 
 // Tensor product of two blocks (both flushed); A and B are freed (or B grows
@@ -135,7 +142,9 @@ sv_status merge(sv_pblock p, PBlk *A, PBlk *B, PBlk **out) {
     if (a + b > nmax)
         return fail(SV_E_INVALID, "entangled block of " + std::to_string(a + b) + " qubits exceeds " +
                                       std::to_string(nmax));
-    if (merge_in_place(p, A, B)) {
+    const int ip = merge_in_place(p, A, B);
+    if (ip < 0) return SV_E_DEVICE;
+    if (ip > 0) {
         remove_block(p, A);
         reindex(p, B);
         *out = B;

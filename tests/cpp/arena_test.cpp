@@ -90,6 +90,28 @@ int main() {
     CHECK(a.grow(lo, 1 << 20));
     CHECK(a.grow(lo, size - 4096));
     CHECK(!a.grow(lo, size - 4096 + 256));
+    // grow_around: room above only, below only, and split between the two
+    a.free(lo);
+    a.free(hi);
+    {
+        const uint64_t U = 1 << 20;
+        char *b1 = (char *)a.alloc(U, U);           // [0, 1M)
+        char *blk = (char *)a.alloc(U, U);          // [1M, 2M)
+        char *b3 = (char *)a.alloc(U, U);           // [2M, 3M)
+        uint64_t k = 99;
+        CHECK(a.grow_around(blk, 2, U, U, &k) == nullptr);   // no room on either side
+        a.free(b3);                                  // room above
+        CHECK(a.grow_around(blk, 4, U, U, &k) == blk && k == 0);
+        a.shrink(blk, U);
+        a.free(b1);                                  // room below too: k = 0 still first
+        char *big = (char *)a.alloc(U << 3, U);      // fill above from 2M on
+        CHECK(big == blk + U);
+        CHECK(a.grow_around(blk, 2, U, U, &k) == blk - U && k == 1);   // only below
+        CHECK(a.used_bytes() == (2 * U) + (U << 3));
+        a.free(blk - U);
+        a.free(big);
+        CHECK(a.free_bytes() == size && a.largest_free() == size);
+    }
     if (failures) return 1;
     std::printf("all checks passed\n");
     return 0;
