@@ -207,7 +207,31 @@ __global__ __launch_bounds__(kTT) void k_tiled(svk::TileArgs a, const svk::TileG
                     const uint32_t j = tid + q * kTT;
                     if (j < size) lds[j] = cmul(ptab[kq[q]], lds[j]);
                 }
+            } else if (sizeof(T) == 8) {
+                // several weights, complex128: terms outer as above, one FP64
+                // angle per amplitude (8 of them per thread)
+                double aq[APT];
+#pragma unroll
+                for (int q = 0; q < APT; ++q) aq[q] = c;
+                for (int t = 0; t < P; ++t) {
+                    const uint32_t lm = terms[t].pm;
+                    if (lm == 0) continue;
+                    const double wt = (__builtin_popcountll(base & terms[t].gm) & 1) ? -terms[t].u[0] : terms[t].u[0];
+#pragma unroll
+                    for (int q = 0; q < APT; ++q)
+                        if (__builtin_popcount((uint32_t)(tid + q * kTT) & lm) & 1) aq[q] += wt;
+                }
+#pragma unroll
+                for (int q = 0; q < APT; ++q) {
+                    const uint32_t j = tid + q * kTT;
+                    if (j >= size) continue;
+                    double sn, cs;
+                    sincos(aq[q], &sn, &cs);
+                    lds[j] = cmul(Cx<T>{(T)cs, (T)sn}, lds[j]);
+                }
             } else {
+                // complex64 (16 amplitudes per thread): amplitudes outer, no
+                // per-amplitude accumulators
 #pragma unroll 1
                 for (int q = 0; q < APT; ++q) {
                     const uint32_t j = tid + q * kTT;

@@ -82,6 +82,34 @@ def test_brickwork_tiled_matches_oracle(ctx, S, O):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("same", [False, True])
+def test_parity_runs_tiled(ctx, S, O, dtype, same):
+    # runs of RZ / RZZ only (parity-form runs): random angles (one FP64 sum per
+    # amplitude) or one angle for the whole run (the phase-table path), on qubits
+    # inside and outside the tiles, between Hadamard layers
+    n = 19
+    rng = np.random.default_rng(11 + same)
+    ops = []
+    for layer in range(3):
+        ops += [("h", (q,), ()) for q in range(n)]
+        g = float(rng.uniform(0, 2 * np.pi))
+        for _ in range(50):
+            a, b = (int(x) for x in rng.choice(n, 2, replace=False))
+            ang = g if same else float(rng.uniform(0, 2 * np.pi))
+            ops.append(("rzz", (a, b), (ang,)) if rng.random() < 0.7 else ("rz", (a,), (ang,)))
+    psi0 = _start(n, 78, dtype)
+    want = O.run(ops, n, psi=psi0.copy())
+    with S.State(ctx, n, dtype) as st:
+        st.copy_in(psi0)
+        st.run(ops, fuse_k=TILED)
+        got = st.copy_out()
+    if dtype == "c128":
+        assert np.max(np.abs(got - want)) <= C128_TOL
+    else:
+        assert infidelity(got, want) <= 1e-5
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_tiled_forward_per_gate_inverse(ctx, S, dtype):
     n = 22
     ops = W.random_circuit(n, 500, seed=4242)
