@@ -168,23 +168,29 @@ __global__ __launch_bounds__(kT) void k_alias_write(const u4 *__restrict__ psi, 
     for (int k = 0; k < kPer && b + k < cnt; ++k) {
         const double s = s_lds[b + k];
         const uint64_t gi = a0 + (uint64_t)k;
-        alias[gi] = gi;
         if (s < 1.0) {
             neum_add(dl, 1.0 - s);
             const uint64_t r = before.nl + lights;
             idx[r] = gi;
             pre[r] = dd_add(before.d, dl);
-            prob[gi] = s;
             ++lights;
         } else {
             neum_add(el, s - 1.0);
             const uint64_t r = nl + (gi - (before.nl + lights));   // heavies before gi
             idx[r] = gi;
             pre[r] = dd_add(before.e, el);
-            prob[gi] = 1.0;
+            s_lds[b + k] = 1.0;   // heavy entries start with prob 1
         }
     }
     (void)incl;
+    __syncthreads();
+    // prob and the identity alias in index order, coalesced (the walk above
+    // gives each thread a contiguous stretch, so its own stores would stride)
+    const uint64_t t0 = (uint64_t)blockIdx.x * kTile;
+    for (int v = threadIdx.x; v < cnt; v += kT) {
+        prob[t0 + v] = s_lds[v];
+        alias[t0 + v] = t0 + v;
+    }
 }
 
 __global__ __launch_bounds__(kT) void k_alias_pair(uint64_t N, const uint64_t *__restrict__ meta,
