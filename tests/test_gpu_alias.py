@@ -96,3 +96,20 @@ def test_errors(ctx, S):
         with pytest.raises(S.SvError):
             st.sample_alias(-1, 0)
         assert st.sample_alias(0, 0).size == 0
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_one_qubit_states(ctx, S, O, dtype):
+    # |1>, |+> and an unbalanced superposition: the smallest tables
+    with S.State(ctx, 1, dtype) as st:
+        st.reset(1)
+        out, prob, alias = st.sample_alias(500, 3, table=True)
+        assert np.all(out == 1) and prob.tolist() == [0.0, 1.0] and alias.tolist() == [1, 1]
+        st.reset(0)
+        st.run([("ry", (0,), (0.6,))])
+        psi = st.copy_out().astype(np.complex128)
+        out, prob, alias = st.sample_alias(4000, 4, table=True)
+    wp, wa = O.alias_build(psi / np.linalg.norm(psi))
+    assert np.max(np.abs(prob - wp)) <= (1e-12 if dtype == "c128" else 1e-6) and alias.tolist() == wa.tolist()
+    assert abs(float(np.mean(out == 1)) - float(np.sin(0.3) ** 2)) <= 5 * np.sqrt(0.25 / 4000)
+

@@ -83,12 +83,13 @@ def test_brickwork_tiled_matches_oracle(ctx, S, O):
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("same", [False, True])
-def test_parity_runs_tiled(ctx, S, O, dtype, same):
+@pytest.mark.parametrize("n", [5, 13, 19])
+def test_parity_runs_tiled(ctx, S, O, n, dtype, same):
     # runs of RZ / RZZ only (parity-form runs): random angles (one FP64 sum per
     # amplitude) or one angle for the whole run (the phase-table path), on qubits
-    # inside and outside the tiles, between Hadamard layers
-    n = 19
-    rng = np.random.default_rng(11 + same)
+    # inside and outside the tiles (one partial tile at n = 5, one full tile at
+    # n = 13), between Hadamard layers
+    rng = np.random.default_rng(11 + same + n)
     ops = []
     for layer in range(3):
         ops += [("h", (q,), ()) for q in range(n)]
