@@ -609,6 +609,8 @@ def main():
     ap.add_argument("--config", default="28q", choices=["28q", "small", "fused", "fused_mfma", "qaoa", "serving", "cost", "pblock", "sampling"],
                     help="28q (default): the headline line; the others print their own JSON line")
     ap.add_argument("--serving-count", type=int, default=10000)
+    ap.add_argument("--sampling-qubits", type=int, nargs="+", default=[16, 20, 24, 28],
+                    help="state sizes of the sampling comparison")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (no sharding or collectives); use --gpus 1",
@@ -624,7 +626,7 @@ def main():
         fn = {"fused": lambda: bench_fused(S), "fused_mfma": lambda: bench_fused_mfma(S), "qaoa": lambda: bench_qaoa(S),
               "serving": lambda: bench_serving(S, count=args.serving_count),
               "small": lambda: bench_small(S), "cost": lambda: bench_cost(S),
-              "pblock": lambda: bench_pblock(S), "sampling": lambda: bench_sampling(S)}[args.config]
+              "pblock": lambda: bench_pblock(S), "sampling": lambda: bench_sampling(S, sizes=tuple(args.sampling_qubits))}[args.config]
         print(json.dumps({"config": args.config, "result": fn()}))
         return
     print("bench: 28-qubit brickwork + QFT, %s, %d warmup + %d timed steps" % (args.dtype, args.warmup, args.steps),

@@ -18,8 +18,12 @@
 //
 // Passes: per-tile counts and sums (k_alias_tiles), one workgroup scanning
 // the tiles (k_alias_scan), per-tile prefixes written with the light and
-// heavy entries compacted in index order (k_alias_write), then the pairing by
-// binary search over the sorted prefixes (k_alias_pair). Draws: k_alias_draw.
+// heavy entries compacted in index order (k_alias_write), then the pairing as
+// a merge of the two sorted prefix sequences (k_alias_part, k_alias_merge).
+// In the merge of D and E with a light entry first on ties, the lights before
+// heavy j are the first light k with D_k > E_j, and the heavies before light
+// k - 1 are the first heavy j with E_j >= D_{k-1}: both queries are positions
+// in one merge. Draws: k_alias_draw.
 #include "sv_device.h"
 #include "sv_kernels.h"
 
@@ -31,6 +35,7 @@ constexpr int kTile = 4096;       // amplitudes per workgroup in the tile passes
 constexpr int kT = 256;           // threads per tile workgroup
 constexpr int kPer = kTile / kT;  // contiguous amplitudes per thread
 constexpr int kScanT = 1024;      // threads of the tile scan
+constexpr uint64_t kMerge = 2048; // merge items per workgroup of the pairing
 
 struct Acc {
     uint64_t nl;   // light entries
@@ -193,40 +198,82 @@ __global__ __launch_bounds__(kT) void k_alias_write(const u4 *__restrict__ psi, 
     }
 }
 
-__global__ __launch_bounds__(kT) void k_alias_pair(uint64_t N, const uint64_t *__restrict__ meta,
-                                                   const uint64_t *__restrict__ idx, const DD *__restrict__ pre,
-                                                   double *__restrict__ prob, uint64_t *__restrict__ alias) {
+// Lights among the first d = w * kMerge items of the merge, for w in
+// [0, nparts]: the smallest i with light i after heavy d - 1 - i
+// (D_i > E_{d-1-i}); the probes stay inside both prefix arrays.
+__global__ __launch_bounds__(kT) void k_alias_part(uint64_t N, const uint64_t *__restrict__ meta,
+                                                   const DD *__restrict__ pre, uint64_t nparts,
+                                                   uint64_t *__restrict__ part) {
     const uint64_t nl = meta[0], nh = N - nl;
     const uint64_t stride = grid_blocks() * kT;
-    for (uint64_t g = block_linear() * kT + threadIdx.x; g < N; g += stride) {
-        if (nh == 0) {   // uniform up to rounding: every slot keeps its outcome
-            prob[g] = 1.0;
-            continue;
+    for (uint64_t w = block_linear() * kT + threadIdx.x; w <= nparts; w += stride) {
+        const uint64_t d = (w * kMerge < N) ? w * kMerge : N;
+        uint64_t lo = d > nh ? d - nh : 0, hi = d < nl ? d : nl;
+        while (lo < hi) {
+            const uint64_t mid = lo + (hi - lo) / 2;
+            if (dd_diff(pre[mid], pre[nl + (d - 1 - mid)]) > 0.0) hi = mid;
+            else lo = mid + 1;
         }
-        if (g < nl) {
-            const DD key = g ? pre[g - 1] : dd_zero();
-            uint64_t lo = 0, hi = nh;   // first heavy with E_j >= key
-            while (lo < hi) {
-                const uint64_t mid = lo + (hi - lo) / 2;
-                if (dd_diff(pre[nl + mid], key) < 0.0) lo = mid + 1;
-                else hi = mid;
-            }
-            alias[idx[g]] = idx[nl + (lo < nh ? lo : nh - 1)];
-        } else {
-            const uint64_t j = g - nl;
-            if (j + 1 == nh) continue;
-            const DD e = pre[g];
-            uint64_t lo = 0, hi = nl;   // first light with D_k > E_j
-            while (lo < hi) {
-                const uint64_t mid = lo + (hi - lo) / 2;
-                if (dd_diff(e, pre[mid]) < 0.0) hi = mid;
-                else lo = mid + 1;
-            }
-            if (lo == nl) continue;
-            const double p = 1.0 - dd_diff(pre[lo], e);
-            prob[idx[g]] = p < 0.0 ? 0.0 : (p > 1.0 ? 1.0 : p);
-            alias[idx[g]] = idx[g + 1];
+        part[w] = lo;
+    }
+}
+
+// Workgroup w takes merge items [w * kMerge, (w + 1) * kMerge): lights
+// [i0, i1) and heavies [h0, h0 + nH), whose prefixes it stages in LDS. Every
+// earlier heavy comes before all of its lights and every earlier light before
+// all of its heavies, so each query is the workgroup's offset plus a binary
+// search in LDS. Light i sets the alias of light i + 1 (light 0 takes heavy 0).
+__global__ __launch_bounds__(kT) void k_alias_merge(uint64_t N, const uint64_t *__restrict__ meta,
+                                                    const uint64_t *__restrict__ part,
+                                                    const uint64_t *__restrict__ idx, const DD *__restrict__ pre,
+                                                    double *__restrict__ prob, uint64_t *__restrict__ alias) {
+    __shared__ DD lds[kMerge];
+    const uint64_t nl = meta[0], nh = N - nl;
+    const uint64_t w = blockIdx.x;
+    const uint64_t d0 = w * kMerge, d1 = (d0 + kMerge < N) ? d0 + kMerge : N;
+    if (nh == 0) {   // uniform up to rounding: every slot keeps its outcome
+        for (uint64_t g = d0 + threadIdx.x; g < d1; g += kT) prob[g] = 1.0;
+        return;
+    }
+    const uint64_t span = d1 - d0, i0 = part[w], i1 = part[w + 1];
+    const uint64_t h0 = d0 - i0;
+    // sorted prefixes give i0 <= i1 <= i0 + span; the clamps keep every
+    // access in bounds whatever the partition holds
+    const uint64_t nL = i1 > i0 ? (i1 - i0 < span ? i1 - i0 : span) : 0;
+    const uint64_t nH = (span - nL < nh - h0) ? span - nL : nh - h0;
+    for (uint64_t v = threadIdx.x; v < nL; v += kT) lds[v] = pre[i0 + v];
+    for (uint64_t v = threadIdx.x; v < nH; v += kT) lds[nL + v] = pre[nl + h0 + v];
+    __syncthreads();
+    if (w == 0 && threadIdx.x == 0 && nl > 0) alias[idx[0]] = idx[nl];
+    for (uint64_t a = threadIdx.x; a < nL; a += kT) {
+        const uint64_t i = i0 + a;
+        if (i + 1 >= nl) continue;
+        const DD key = lds[a];
+        uint64_t lo = 0, hi = nH;   // local heavies with E < D_i
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi) / 2;
+            if (dd_diff(lds[nL + mid], key) < 0.0) lo = mid + 1;
+            else hi = mid;
         }
+        const uint64_t h = h0 + lo;
+        alias[idx[i + 1]] = idx[nl + (h < nh ? h : nh - 1)];
+    }
+    for (uint64_t b = threadIdx.x; b < nH; b += kT) {
+        const uint64_t j = h0 + b;
+        if (j + 1 >= nh) continue;
+        const DD e = lds[nL + b];
+        uint64_t lo = 0, hi = nL;   // local lights with D <= E_j
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi) / 2;
+            if (dd_diff(e, lds[mid]) < 0.0) hi = mid;
+            else lo = mid + 1;
+        }
+        const uint64_t i = i0 + lo;
+        if (i >= nl) continue;   // never exhausted: prob stays 1
+        const DD di = lo < nL ? lds[lo] : pre[i];
+        const double p = 1.0 - dd_diff(di, e);
+        prob[idx[nl + j]] = p < 0.0 ? 0.0 : (p > 1.0 ? 1.0 : p);
+        alias[idx[nl + j]] = idx[nl + j + 1];
     }
 }
 
@@ -247,8 +294,10 @@ dim3 capped(uint64_t items) {
     return dim3((unsigned)(nb < (1ull << 16) ? nb : (1ull << 16)));
 }
 
+uint64_t nparts(uint64_t N) { return (N + kMerge - 1) / kMerge; }
+
 struct AliasLayout {
-    uint64_t prob, alias, idx, pre, rec, meta, total;
+    uint64_t prob, alias, idx, pre, rec, part, meta, total;
 };
 
 AliasLayout layout(int n) {
@@ -259,7 +308,8 @@ AliasLayout layout(int n) {
     L.idx = L.alias + 8 * N;
     L.pre = L.idx + 8 * N;
     L.rec = L.pre + 16 * N;
-    L.meta = L.rec + ((sizeof(Acc) * ntiles + 255) & ~255ull);
+    L.part = L.rec + ((sizeof(Acc) * ntiles + 255) & ~255ull);
+    L.meta = L.part + ((8 * (nparts(N) + 1) + 255) & ~255ull);
     L.total = L.meta + 256;
     return L;
 }
@@ -300,7 +350,10 @@ hipError_t launch_alias_build(const void *psi, int n, int is_c64, void *ws, void
     else
         hipLaunchKernelGGL(k_alias_write<double>, dim3((unsigned)ntiles), dim3(kT), 0, s, (const u4 *)psi, n, norm2,
                            rec, meta, prob, alias, idx, pre);
-    hipLaunchKernelGGL(k_alias_pair, capped(N), dim3(kT), 0, s, N, meta, idx, pre, prob, alias);
+    uint64_t *part = (uint64_t *)(w + L.part);
+    const uint64_t np = nparts(N);
+    hipLaunchKernelGGL(k_alias_part, capped(np + 1), dim3(kT), 0, s, N, meta, pre, np, part);
+    hipLaunchKernelGGL(k_alias_merge, dim3((unsigned)np), dim3(kT), 0, s, N, meta, part, idx, pre, prob, alias);
     return hipGetLastError();
 }
 
