@@ -16,8 +16,9 @@
 // Both prefixes are compensated (value + error term), so prob keeps FP64
 // accuracy however large the prefixes grow.
 //
-// Passes: per-tile counts and sums (k_alias_tiles), one workgroup scanning
-// the tiles (k_alias_scan), per-tile prefixes written with the light and
+// Passes: per-tile counts and sums (k_alias_tiles), the tile records scanned
+// in groups of 1024 and the group totals by one workgroup (k_alias_scan_grp,
+// k_alias_scan), per-tile prefixes written with the light and
 // heavy entries compacted in index order (k_alias_write), then the pairing as
 // a merge of the two sorted prefix sequences (k_alias_part, k_alias_merge).
 // In the merge of D and E with a light entry first on ties, the lights before
@@ -31,7 +32,7 @@ using namespace svd;
 
 namespace {
 
-constexpr int kTile = 4096;       // amplitudes per workgroup in the tile passes
+constexpr int kTile = 2048;       // amplitudes per workgroup in the tile passes
 constexpr int kT = 256;           // threads per tile workgroup
 constexpr int kPer = kTile / kT;  // contiguous amplitudes per thread
 constexpr int kScanT = 1024;      // threads of the tile scan
@@ -130,7 +131,18 @@ __global__ __launch_bounds__(kT) void k_alias_tiles(const u4 *__restrict__ psi, 
     if (threadIdx.x == kT - 1) rec[blockIdx.x] = tot;
 }
 
-// Exclusive scan of the tile records in place; meta[0] = number of light entries.
+// Exclusive scan of the tile records within groups of kScanT tiles, in place
+// (one coalesced record per thread); grp[g] = total of group g.
+__global__ __launch_bounds__(kScanT) void k_alias_scan_grp(Acc *__restrict__ rec, uint64_t ntiles,
+                                                           Acc *__restrict__ grp) {
+    __shared__ Acc buf[kScanT];
+    const uint64_t i = (uint64_t)blockIdx.x * kScanT + threadIdx.x;
+    const Acc incl = block_incl_scan<kScanT>(i < ntiles ? rec[i] : acc_zero(), buf);
+    if (i < ntiles) rec[i] = threadIdx.x ? buf[threadIdx.x - 1] : acc_zero();
+    if (threadIdx.x == kScanT - 1) grp[blockIdx.x] = incl;
+}
+
+// Exclusive scan of the group totals in place; meta[0] = number of light entries.
 __global__ __launch_bounds__(kScanT) void k_alias_scan(Acc *__restrict__ rec, uint64_t ntiles,
                                                        uint64_t *__restrict__ meta) {
     __shared__ Acc buf[kScanT];
@@ -150,49 +162,64 @@ __global__ __launch_bounds__(kScanT) void k_alias_scan(Acc *__restrict__ rec, ui
     if (threadIdx.x == kScanT - 1) meta[0] = incl.nl;
 }
 
+// LDS of the write pass: the scan buffer is done with before the compacted
+// prefixes are staged, so the two share their space.
+union WriteStage {
+    Acc buf[kT];
+    DD pre[kTile];
+};
+
+// Per-entry prefixes, compacted: lights in index order at [0, nl), heavies at
+// [nl, N). Each thread walks its contiguous amplitudes and stages the light
+// and heavy entries in LDS at their ranks within the tile (lights first);
+// the tile's two runs, its prob values and identity aliases are then stored
+// coalesced.
 template <typename T>
 __global__ __launch_bounds__(kT) void k_alias_write(const u4 *__restrict__ psi, int n,
                                                     const double *__restrict__ norm2, const Acc *__restrict__ rec,
-                                                    const uint64_t *__restrict__ meta, double *__restrict__ prob,
-                                                    uint64_t *__restrict__ alias, uint64_t *__restrict__ idx,
-                                                    DD *__restrict__ pre) {
+                                                    const Acc *__restrict__ grp, const uint64_t *__restrict__ meta,
+                                                    double *__restrict__ prob, uint64_t *__restrict__ alias,
+                                                    uint64_t *__restrict__ idx, DD *__restrict__ pre) {
     __shared__ double s_lds[kTile];
-    __shared__ Acc buf[kT];
+    __shared__ uint16_t l_idx[kTile];
+    __shared__ WriteStage st;
     const double scale = (double)(1ull << n) / norm2[0];
     const int cnt = load_tile<T>(psi, n, blockIdx.x, scale, s_lds);
     const Acc mine = thread_acc(s_lds, cnt);
-    const Acc incl = block_incl_scan<kT>(mine, buf);
-    Acc before = threadIdx.x ? buf[threadIdx.x - 1] : acc_zero();
-    before = acc_cat(rec[blockIdx.x], before);
-    const uint64_t nl = meta[0];
-    const uint64_t a0 = (uint64_t)blockIdx.x * kTile + (uint64_t)threadIdx.x * kPer;
+    (void)block_incl_scan<kT>(mine, st.buf);
+    const Acc local = threadIdx.x ? st.buf[threadIdx.x - 1] : acc_zero();   // earlier threads of the tile
+    const int tile_nl = (int)st.buf[kT - 1].nl;
+    const Acc tile_off = acc_cat(grp[blockIdx.x / kScanT], rec[blockIdx.x]);
+    const Acc before = acc_cat(tile_off, local);
+    __syncthreads();   // the scan buffer is read; its space now stages prefixes
     const int b = threadIdx.x * kPer;
-    // running prefixes of this thread's own values, joined to `before`
+    const int lb = (int)local.nl;
     DD dl = dd_zero(), el = dd_zero();
-    uint64_t lights = 0;
+    int lights = 0;
     for (int k = 0; k < kPer && b + k < cnt; ++k) {
         const double s = s_lds[b + k];
-        const uint64_t gi = a0 + (uint64_t)k;
         if (s < 1.0) {
             neum_add(dl, 1.0 - s);
-            const uint64_t r = before.nl + lights;
-            idx[r] = gi;
-            pre[r] = dd_add(before.d, dl);
+            const int r = lb + lights;
+            st.pre[r] = dd_add(before.d, dl);
+            l_idx[r] = (uint16_t)(b + k);
             ++lights;
         } else {
             neum_add(el, s - 1.0);
-            const uint64_t r = nl + (gi - (before.nl + lights));   // heavies before gi
-            idx[r] = gi;
-            pre[r] = dd_add(before.e, el);
+            const int r = tile_nl + (b + k - (lb + lights));   // heavies of the tile before this one
+            st.pre[r] = dd_add(before.e, el);
+            l_idx[r] = (uint16_t)(b + k);
             s_lds[b + k] = 1.0;   // heavy entries start with prob 1
         }
     }
-    (void)incl;
     __syncthreads();
-    // prob and the identity alias in index order, coalesced (the walk above
-    // gives each thread a contiguous stretch, so its own stores would stride)
+    const uint64_t nl = meta[0];
     const uint64_t t0 = (uint64_t)blockIdx.x * kTile;
+    const uint64_t gl = tile_off.nl, gh = nl + (t0 - tile_off.nl);   // where the tile's runs start
     for (int v = threadIdx.x; v < cnt; v += kT) {
+        const uint64_t r = v < tile_nl ? gl + (uint64_t)v : gh + (uint64_t)(v - tile_nl);
+        idx[r] = t0 + l_idx[v];
+        pre[r] = st.pre[v];
         prob[t0 + v] = s_lds[v];
         alias[t0 + v] = t0 + v;
     }
@@ -295,9 +322,10 @@ dim3 capped(uint64_t items) {
 }
 
 uint64_t nparts(uint64_t N) { return (N + kMerge - 1) / kMerge; }
+uint64_t ngroups(uint64_t ntiles) { return (ntiles + kScanT - 1) / kScanT; }
 
 struct AliasLayout {
-    uint64_t prob, alias, idx, pre, rec, part, meta, total;
+    uint64_t prob, alias, idx, pre, rec, grp, part, meta, total;
 };
 
 AliasLayout layout(int n) {
@@ -308,7 +336,8 @@ AliasLayout layout(int n) {
     L.idx = L.alias + 8 * N;
     L.pre = L.idx + 8 * N;
     L.rec = L.pre + 16 * N;
-    L.part = L.rec + ((sizeof(Acc) * ntiles + 255) & ~255ull);
+    L.grp = L.rec + ((sizeof(Acc) * ntiles + 255) & ~255ull);
+    L.part = L.grp + ((sizeof(Acc) * ngroups(ntiles) + 255) & ~255ull);
     L.meta = L.part + ((8 * (nparts(N) + 1) + 255) & ~255ull);
     L.total = L.meta + 256;
     return L;
@@ -340,16 +369,19 @@ hipError_t launch_alias_build(const void *psi, int n, int is_c64, void *ws, void
     else
         hipLaunchKernelGGL(k_alias_tiles<double>, dim3((unsigned)ntiles), dim3(kT), 0, s, (const u4 *)psi, n, norm2,
                            rec);
-    hipLaunchKernelGGL(k_alias_scan, dim3(1), dim3(kScanT), 0, s, rec, ntiles, meta);
+    Acc *grp = (Acc *)(w + L.grp);
+    const uint64_t ng = ngroups(ntiles);
+    hipLaunchKernelGGL(k_alias_scan_grp, dim3((unsigned)ng), dim3(kScanT), 0, s, rec, ntiles, grp);
+    hipLaunchKernelGGL(k_alias_scan, dim3(1), dim3(kScanT), 0, s, grp, ng, meta);
     double *prob = (double *)(w + L.prob);
     uint64_t *alias = (uint64_t *)(w + L.alias), *idx = (uint64_t *)(w + L.idx);
     DD *pre = (DD *)(w + L.pre);
     if (is_c64)
         hipLaunchKernelGGL(k_alias_write<float>, dim3((unsigned)ntiles), dim3(kT), 0, s, (const u4 *)psi, n, norm2,
-                           rec, meta, prob, alias, idx, pre);
+                           rec, grp, meta, prob, alias, idx, pre);
     else
         hipLaunchKernelGGL(k_alias_write<double>, dim3((unsigned)ntiles), dim3(kT), 0, s, (const u4 *)psi, n, norm2,
-                           rec, meta, prob, alias, idx, pre);
+                           rec, grp, meta, prob, alias, idx, pre);
     uint64_t *part = (uint64_t *)(w + L.part);
     const uint64_t np = nparts(N);
     hipLaunchKernelGGL(k_alias_part, capped(np + 1), dim3(kT), 0, s, N, meta, pre, np, part);
