@@ -1,9 +1,10 @@
 """Parity at the full sizes of the measured workloads, through properties that
 hold at any size and outputs computable one by one: 28-qubit brickwork mirror
 and norm, 28-qubit QFT against its closed form on sampled outputs, 30-qubit
-QAOA p=1 against the closed form, and the 33-qubit complex128 / 34-qubit
+QAOA p=1 against the closed form, the 33-qubit complex128 / 34-qubit
 complex64 fused and tiled paths by cross-mirror (fused blocks or tiled passes
-forward, per-gate inverse). Per-gate, fused and tiled runs are all checked."""
+forward, per-gate inverse), and both samplers at 28 qubits against the oracle
+on the state read back. Per-gate, fused and tiled runs are all checked."""
 import math
 
 import numpy as np
@@ -96,3 +97,41 @@ def test_fused_cross_mirror_full_size(big_ctx, S, n, dtype, fuse_k):
         a0 = st.amplitudes([0])[0]
     tol = 1e-12 if dtype == "c128" else 1e-5
     assert 1.0 - abs(a0) ** 2 <= tol
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_sampling_28q_coupled_to_oracle(ctx, S, O, dtype):
+    # the inverse-CDF sampler at the measured size and shot count (4096 shots
+    # of a 28-qubit brickwork state), against the oracle's inverse CDF of the
+    # same state read back: both draw U01(seed, s) for shot s, so the outcomes
+    # agree but where u lands between the two CDFs (expected count ~0)
+    n, shots = 28, 4096
+    with S.State(ctx, n, dtype) as st:
+        st.run(W.brickwork(n, 6, seed=SEED))
+        got = st.sample(shots, SEED + 1)
+        psi = st.copy_out().astype(np.complex128)
+    want = O.sample(psi, shots, SEED + 1)
+    assert got.shape == (shots,) and np.all(got < (1 << n))
+    assert int(np.count_nonzero(got != want)) <= 1
+
+
+def test_alias_28q_table_and_draws(ctx, S, O):
+    # the whole 2^28-entry alias table against the oracle's sweep over the same
+    # state, and 10^5 draws. Tolerance on prob: a heavy entry's prob is
+    # 1 - (D_k - E_j) with prefixes of up to N terms, so an ulp of difference
+    # in the two squared norms moves it by up to about 2^-53 N per ulp; two
+    # ulps are allowed
+    n, shots = 28, 100000
+    N = 1 << n
+    with S.State(ctx, n, "c128") as st:
+        st.run(W.brickwork(n, 6, seed=SEED))
+        out, prob, alias = st.sample_alias(shots, SEED + 2, table=True)
+        psi = st.copy_out()
+    wp, wa = O.alias_build(psi)
+    assert np.max(np.abs(prob - wp)) <= 1e-9 + 2 * 2.0**-53 * N
+    assert int(np.count_nonzero(alias != wa)) <= 2 + N // 10**6
+    p = np.abs(psi) ** 2
+    assert np.all(prob[p == 0] == 0)
+    ref = O.alias_sample(wp, wa, shots, SEED + 2)
+    assert int(np.count_nonzero(out != ref)) <= 2
+    assert np.all(out < N)
