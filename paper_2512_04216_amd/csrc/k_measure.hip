@@ -19,6 +19,7 @@ using namespace svd;
 namespace {
 
 constexpr int kLeafBits = 10;           // amplitudes per leaf = 1024
+constexpr int kRowsPerLeaf = 16;        // rows (64 loads of 16 bytes) per leaf, complex128; 8 for complex64
 constexpr int kChunk = 1024;            // leaves per scan chunk
 constexpr int kScanThreads = 256;
 constexpr int kMaxRedBlocks = 1024;     // partial sums of a reduction
@@ -26,7 +27,7 @@ constexpr int kTB = 16;                 // Z terms per reduction pass
 
 struct WS {
     uint64_t nleaf, nchunk, nred;
-    uint64_t off_leafsum, off_leafcdf, off_chunk, off_chunkpre, off_part, off_res;
+    uint64_t off_leafsum, off_leafcdf, off_chunk, off_chunkpre, off_part, off_res, off_rowsum;
 };
 
 __host__ __device__ inline uint64_t nleaf_of(int n) { return n > kLeafBits ? (1ull << (n - kLeafBits)) : 1ull; }
@@ -44,12 +45,13 @@ inline WS ws_layout(int n) {
     w.off_chunkpre = w.off_chunk + 2 * w.nchunk;
     w.off_part = w.off_chunkpre + 2 * w.nchunk;
     w.off_res = w.off_part + w.nred * (kTB + 1) * 2;
+    w.off_rowsum = w.off_res + 2 * (kTB + 1) + 8;
     return w;
 }
 
 inline uint64_t ws_doubles(int n) {
     WS w = ws_layout(n);
-    return w.off_res + 2 * (kTB + 1) + 8;
+    return w.off_rowsum + w.nleaf * kRowsPerLeaf;
 }
 
 // SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): output s (from 0) of the
@@ -74,8 +76,30 @@ __device__ inline double prob(const Q &q, int r) {
 }
 
 // ---- leaf sums ---------------------------------------------------------
+// Inclusive scan of one double per lane across the wavefront (fixed order).
+__device__ inline double wave_incl_scan(double v, int lane) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int src = lane >= off ? lane - off : lane;
+        union {
+            double d;
+            int w[2];
+        } u;
+        u.d = v;
+        u.w[0] = __builtin_amdgcn_ds_bpermute(src << 2, u.w[0]);
+        u.w[1] = __builtin_amdgcn_ds_bpermute(src << 2, u.w[1]);
+        if (lane >= off) v = u.d + v;
+    }
+    return v;
+}
+
+// One wavefront per leaf: the leaf's compensated sum, and the plain total of
+// each row of the leaf (64 loads of 16 bytes) from the same wave scan that
+// k_sample runs over a row, so that its running sums over rows can start at
+// any row with the carry a scan from the leaf's start would have there.
 template <typename T>
-__global__ __launch_bounds__(256) void k_leafsum(const u4 *__restrict__ psi, int n, double *__restrict__ leafsum) {
+__global__ __launch_bounds__(256) void k_leafsum(const u4 *__restrict__ psi, int n, double *__restrict__ leafsum,
+                                                 double *__restrict__ rowsum) {
     constexpr int E = Amp<T>::E;
     const uint64_t leaf = wave_id_xcd();
     const uint64_t nleaf = nleaf_of(n);
@@ -84,12 +108,22 @@ __global__ __launch_bounds__(256) void k_leafsum(const u4 *__restrict__ psi, int
     const uint64_t leaf_amps = n > kLeafBits ? (1ull << kLeafBits) : (1ull << n);
     const uint64_t nvec = (leaf_amps + E - 1) / E;
     const u4 *p = psi + leaf * ((1ull << kLeafBits) / E);
+    double *rs = rowsum + leaf * kRowsPerLeaf;
     DD acc = dd_zero();
-    for (uint64_t vi = lane; vi < nvec; vi += 64) {
+    for (uint64_t row = 0; row * 64 < nvec; ++row) {
+        const uint64_t vi = row * 64 + lane;
         Q q;
-        q.v = ld_nt(p + vi);
+        q.v = u4{0, 0, 0, 0};
+        if (vi < nvec) q.v = ld_nt(p + vi);
+        double lt = 0.0;
 #pragma unroll
-        for (int r = 0; r < E; ++r) neum_add(acc, prob<T>(q, r));
+        for (int r = 0; r < E; ++r) {
+            const double pr = prob<T>(q, r);
+            if (vi < nvec) neum_add(acc, pr);
+            lt += pr;
+        }
+        const double incl = wave_incl_scan(lt, lane);
+        if (lane == 63) rs[row] = incl;
     }
     acc = wave_reduce_dd(acc, lane);
     if (lane == 0) leafsum[leaf] = dd_value(acc);
@@ -181,22 +215,6 @@ __global__ __launch_bounds__(kScanThreads) void k_leaf_scan(const double *__rest
 }
 
 // ---- shot resolution ---------------------------------------------------
-__device__ inline double wave_incl_scan(double v, int lane) {
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int src = lane >= off ? lane - off : lane;
-        union {
-            double d;
-            int w[2];
-        } u;
-        u.d = v;
-        u.w[0] = __builtin_amdgcn_ds_bpermute(src << 2, u.w[0]);
-        u.w[1] = __builtin_amdgcn_ds_bpermute(src << 2, u.w[1]);
-        if (lane >= off) v = u.d + v;
-    }
-    return v;
-}
-
 __device__ inline double read_lane_d(double v, int l) {
     union {
         double d;
@@ -210,7 +228,8 @@ __device__ inline double read_lane_d(double v, int l) {
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_sample(const u4 *__restrict__ psi, int n, const double *__restrict__ leafcdf,
-                                                int64_t shots, uint64_t seed, uint64_t s0,
+                                                const double *__restrict__ rowsum, int64_t shots, uint64_t seed,
+                                                uint64_t s0,
                                                 const uint64_t *__restrict__ counters, uint64_t *__restrict__ out) {
     constexpr int E = Amp<T>::E;
     const uint64_t sl = wave_id_global();
@@ -245,9 +264,28 @@ __global__ __launch_bounds__(256) void k_sample(const u4 *__restrict__ psi, int 
     const uint64_t leaf_amps = n > kLeafBits ? (1ull << kLeafBits) : (1ull << n);
     const uint64_t nvec = (leaf_amps + E - 1) / E;
     const u4 *p = psi + leaf * ((1ull << kLeafBits) / E);
+    // start at the first row whose running total exceeds rl, with the carry
+    // a scan from row 0 would have there (same row totals, same order of
+    // additions); when rounding leaves rl at the leaf's total, or on the
+    // clamp, the scan starts at row 0
+    const uint64_t nrows = (nvec + 63) / 64;
+    uint64_t row0 = 0;
     double carry = 0.0;
+    if (!clamp) {
+        const double t = (uint64_t)lane < nrows ? rowsum[leaf * kRowsPerLeaf + (uint64_t)lane] : 0.0;
+        double c = 0.0;
+        for (uint64_t rr = 0; rr < nrows; ++rr) {
+            const double next = c + read_lane_d(t, (int)rr);
+            if (next > rl) {
+                row0 = rr;
+                carry = c;
+                break;
+            }
+            c = next;
+        }
+    }
     int64_t found = -1, lastnz = -1;
-    for (uint64_t row = 0; row * 64 < nvec; ++row) {
+    for (uint64_t row = row0; row * 64 < nvec; ++row) {
         const uint64_t vi = row * 64 + lane;
         double pr[E];
         Q q;
@@ -523,9 +561,11 @@ hipError_t launch_cdf(const void *psi, int n, int is_c64, void *ws, hipStream_t 
     double *d = wsd(ws);
     const uint64_t lblocks = (w.nleaf + 3) / 4;
     if (is_c64)
-        hipLaunchKernelGGL(k_leafsum<float>, grid_for(lblocks), dim3(256), 0, s, (const u4 *)psi, n, d + w.off_leafsum);
+        hipLaunchKernelGGL(k_leafsum<float>, grid_for(lblocks), dim3(256), 0, s, (const u4 *)psi, n, d + w.off_leafsum,
+                           d + w.off_rowsum);
     else
-        hipLaunchKernelGGL(k_leafsum<double>, grid_for(lblocks), dim3(256), 0, s, (const u4 *)psi, n, d + w.off_leafsum);
+        hipLaunchKernelGGL(k_leafsum<double>, grid_for(lblocks), dim3(256), 0, s, (const u4 *)psi, n, d + w.off_leafsum,
+                           d + w.off_rowsum);
     hipLaunchKernelGGL(k_chunk_total, dim3((unsigned)w.nchunk), dim3(kScanThreads), 0, s, d + w.off_leafsum, w.nleaf,
                        d + w.off_chunk);
     hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kScanThreads), 0, s, d + w.off_chunk, w.nchunk, d + w.off_chunkpre,
@@ -561,11 +601,11 @@ hipError_t launch_sample_at(const void *psi, int n, int is_c64, const void *ws, 
     const double *d = wsd(ws);
     const unsigned blocks = (unsigned)((shots + 3) / 4);
     if (is_c64)
-        hipLaunchKernelGGL(k_sample<float>, dim3(blocks), dim3(256), 0, s, (const u4 *)psi, n, d + w.off_leafcdf, shots,
-                           seed, s0, counters_dev, out_dev);
+        hipLaunchKernelGGL(k_sample<float>, dim3(blocks), dim3(256), 0, s, (const u4 *)psi, n, d + w.off_leafcdf,
+                           d + w.off_rowsum, shots, seed, s0, counters_dev, out_dev);
     else
         hipLaunchKernelGGL(k_sample<double>, dim3(blocks), dim3(256), 0, s, (const u4 *)psi, n, d + w.off_leafcdf,
-                           shots, seed, s0, counters_dev, out_dev);
+                           d + w.off_rowsum, shots, seed, s0, counters_dev, out_dev);
     return hipGetLastError();
 }
 
