@@ -415,6 +415,52 @@ def bench_sampling(S, sizes=(16, 20, 24, 28), shot_counts=(10**4, 10**6, 10**7))
     return out
 
 
+def bench_midcircuit(S, n=26, shots=1000, layers=(6, 4, 4, 4)):
+    """Shots of a circuit with mid-circuit measurements (sv_run_shots, Sec.
+    III-B: run once up to the first measurement, then clone the state where
+    the shots' outcomes part). A 26-qubit complex128 brickwork in four
+    segments; after each of the first three, one qubit is measured into a
+    classical bit and a gate conditioned on that bit follows (a teleportation-
+    style correction). The branches are the distinct outcome prefixes; a
+    simulator that re-ran every shot from the start would take about `shots`
+    times one trajectory."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+
+    ops = []
+    for seg, depth in enumerate(layers):
+        ops += W.brickwork(n, depth, seed=SEED + 10 + seg)
+        if seg < len(layers) - 1:
+            q = 3 * seg + 1
+            ops += [("measure", (q, seg), ()), W.circuits.c_if(("x", (q + 1,), ()), seg, 1)]
+    gates = sum(1 for o in ops if o[0] != "measure")
+    ctx = S.Context(arena_bytes=24 << 30)
+    out = {"qubits": n, "dtype": "c128", "ops": len(ops), "gates": gates, "measurements": len(layers) - 1,
+           "shots": shots}
+    for fk, key in ((0, "per_gate"), (S.SV_FUSE_TILED, "tiled")):
+        st = S.State(ctx, n, "c128")
+        st.run_shots(ops, 1, 1, fuse_k=fk, samples=False)            # warm
+        torch.cuda.synchronize()
+        st.reset(0)
+        t0 = time.perf_counter()
+        st.run_shots(ops, 1, SEED, fuse_k=fk, samples=True)
+        t_one = time.perf_counter() - t0
+        st.reset(0)
+        t0 = time.perf_counter()
+        cl, sm = st.run_shots(ops, shots, SEED, fuse_k=fk, samples=True)
+        t_all = time.perf_counter() - t0
+        st.close()
+        out[key] = {"seconds": round(t_all, 3), "one_trajectory_s": round(t_one, 3),
+                    "branches": int(np.unique(cl).size),
+                    "rerun_every_shot_estimate_s": round(shots * t_one, 1),
+                    "speedup_vs_rerun": round(shots * t_one / t_all, 1)}
+        print("bench: mid-circuit %s done in %.3f s" % (key, t_all), file=sys.stderr, flush=True)
+    ctx.close()
+    return out
+
+
 def bench_small(S, reps=200, batch=2000):
     """12-qubit brickwork, 20 layers (350 gates), complex128, 1024 shots: a
     latency-bound circuit (the whole state is 64 KiB). Microseconds per
@@ -606,7 +652,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c64", action="store_true", help="skip the complex64 side measurement")
     ap.add_argument("--no-trace", action="store_true")
-    ap.add_argument("--config", default="28q", choices=["28q", "small", "fused", "fused_mfma", "qaoa", "serving", "cost", "pblock", "sampling"],
+    ap.add_argument("--config", default="28q", choices=["28q", "small", "fused", "fused_mfma", "qaoa", "serving", "cost", "pblock", "sampling", "midcircuit"],
                     help="28q (default): the headline line; the others print their own JSON line")
     ap.add_argument("--serving-count", type=int, default=10000)
     ap.add_argument("--sampling-qubits", type=int, nargs="+", default=[16, 20, 24, 28],
@@ -626,7 +672,8 @@ def main():
         fn = {"fused": lambda: bench_fused(S), "fused_mfma": lambda: bench_fused_mfma(S), "qaoa": lambda: bench_qaoa(S),
               "serving": lambda: bench_serving(S, count=args.serving_count),
               "small": lambda: bench_small(S), "cost": lambda: bench_cost(S),
-              "pblock": lambda: bench_pblock(S), "sampling": lambda: bench_sampling(S, sizes=tuple(args.sampling_qubits))}[args.config]
+              "pblock": lambda: bench_pblock(S), "sampling": lambda: bench_sampling(S, sizes=tuple(args.sampling_qubits)),
+              "midcircuit": lambda: bench_midcircuit(S)}[args.config]
         print(json.dumps({"config": args.config, "result": fn()}))
         return
     print("bench: 28-qubit brickwork + QFT, %s, %d warmup + %d timed steps" % (args.dtype, args.warmup, args.steps),
