@@ -2,7 +2,8 @@
 sequential sweep: the same table (prob within FP64 rounding, aliases equal
 except where a comparison lands within rounding), the alias-table mass
 identity on the device table, the same draws, and the degenerate states
-(point mass, uniform, sparse), up to a 26-qubit state."""
+(point mass, uniform, sparse), up to a 26-qubit state; on inputs where FP64
+arithmetic is exact, the same table bit for bit."""
 import numpy as np
 import pytest
 
@@ -113,3 +114,23 @@ def test_one_qubit_states(ctx, S, O, dtype):
     assert np.max(np.abs(prob - wp)) <= (1e-12 if dtype == "c128" else 1e-6) and alias.tolist() == wa.tolist()
     assert abs(float(np.mean(out == 1)) - float(np.sin(0.3) ** 2)) <= 5 * np.sqrt(0.25 / 4000)
 
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [2, 5, 11, 12, 14, 16])
+def test_dyadic_states_bit_exact(ctx, S, O, n, dtype):
+    # amplitudes whose squared norms, norm, s values and prefix sums are all
+    # exact in FP64 (and whose amplitudes are exact in FP32): the device's
+    # table must equal the oracle's sweep bit for bit, the order of equal
+    # prefixes included, across several tiles and merge parts
+    from test_oracle_alias import _dyadic_state
+    rng = np.random.default_rng(500 + n)
+    for mode in ("random", "sparse", "outlier"):
+        psi = _dyadic_state(n, rng, mode)
+        with S.State(ctx, n, dtype) as st:
+            st.copy_in(psi)
+            out, prob, alias = st.sample_alias(5000, 13, table=True)
+        wp, wa = O.alias_build(psi)
+        assert prob.tolist() == wp.tolist()
+        assert alias.tolist() == wa.tolist()
+        assert out.tolist() == O.alias_sample(wp, wa, 5000, 13).tolist()
