@@ -1,6 +1,7 @@
 """GPU parity of the FP64 measurement path: squared norm, renormalisation,
 shot sampling (coupled to the oracle's sampler through the shared counter-based
-generator) and Pauli expectation values."""
+generator; outcome for outcome on inputs where FP64 arithmetic is exact) and
+Pauli expectation values."""
 import math
 
 import numpy as np
@@ -62,6 +63,25 @@ def test_sampling_edge_cases(ctx, S, O):
         assert abs(int(np.sum(out == 0)) - 10000) <= 5 * math.sqrt(20000) / 2
         # the shot counter continues across calls: shots 0..9 equal the first 10 of 20000
         assert np.array_equal(st.sample(10, 6), out[:10])
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [4, 10, 12, 16, 20])
+def test_sampling_exact_on_dyadic_states(ctx, S, O, n, dtype):
+    # amplitudes (x + iy)/1024 with small integers whose squares add up to a
+    # power of two: probabilities, leaf sums, the CDF, the row totals and the
+    # running sums inside a leaf are exact in FP64 on both sides, so every
+    # shot must give the oracle's outcome (many leaves and rows at 16 and 20
+    # qubits, zeros and ties included)
+    from test_oracle_alias import _dyadic_state
+    rng = np.random.default_rng(700 + n)
+    for mode in ("random", "sparse", "outlier"):
+        psi = _dyadic_state(n, rng, mode)
+        with S.State(ctx, n, dtype) as st:
+            st.copy_in(psi)
+            got = st.sample(20000, 31 + n)
+        want = O.sample(psi, 20000, 31 + n)
+        assert got.tolist() == want.tolist()
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
