@@ -1,7 +1,7 @@
 """GPU parity of the FP64 measurement path: squared norm, renormalisation,
 shot sampling (coupled to the oracle's sampler through the shared counter-based
 generator; outcome for outcome on inputs where FP64 arithmetic is exact) and
-Pauli expectation values."""
+Pauli expectation values (equal on such inputs)."""
 import math
 
 import numpy as np
@@ -99,6 +99,26 @@ def test_expectations_match_oracle(ctx, S, O, n, dtype):
     tol = 1e-12 if dtype == "c128" else 2 * math.sqrt(1e-5)
     assert np.max(np.abs(vals - want)) <= tol
     assert abs(wsum - sum(c * w for (_, _, c), w in zip(terms, want))) <= tol * len(terms)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [3, 8, 12, 16])
+def test_expectations_exact_on_dyadic_states(ctx, S, O, n, dtype):
+    # on amplitudes (x + iy)/1024 with small integers whose squares add up to
+    # a power of two every product and partial sum is exact in FP64, so each
+    # <P> is the same dyadic rational on both sides: Z-only batches over
+    # several passes, X/Y strings and the identity
+    from test_oracle_alias import _dyadic_state
+    rng = np.random.default_rng(900 + n)
+    psi = _dyadic_state(n, rng, "random")
+    terms = W.random_paulis(n, 24, seed=90 + n)
+    terms += [(0, int(z), 1.0) for z in rng.integers(0, 1 << n, 20)]
+    terms += [(0, 0, 1.0)]
+    with S.State(ctx, n, dtype) as st:
+        st.copy_in(psi)
+        vals, _ = st.expect(terms)
+    want = [O.expect(psi, x, z).real for x, z, _ in terms]
+    assert vals.tolist() == want
 
 
 def test_qaoa_energy_matches_oracle(ctx, S, O):
