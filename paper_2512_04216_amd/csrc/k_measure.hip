@@ -93,10 +93,47 @@ __device__ inline double wave_incl_scan(double v, int lane) {
     return v;
 }
 
+__device__ inline double read_lane_d(double v, int l) {
+    union {
+        double d;
+        int w[2];
+    } u;
+    u.d = v;
+    u.w[0] = __builtin_amdgcn_readlane(u.w[0], l);
+    u.w[1] = __builtin_amdgcn_readlane(u.w[1], l);
+    return u.d;
+}
+
+// A DPP move of a double within each row of 16 lanes (CTRL: the DPP control).
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+    union {
+        double d;
+        int w[2];
+    } u;
+    u.d = v;
+    u.w[0] = __builtin_amdgcn_update_dpp(0, u.w[0], CTRL, 0xF, 0xF, false);
+    u.w[1] = __builtin_amdgcn_update_dpp(0, u.w[1], CTRL, 0xF, 0xF, false);
+    return u.d;
+}
+
+// The value wave_incl_scan leaves in lane 63: the sum over the 64 lanes as a
+// balanced tree of aligned blocks (pairs, quads, 8, 16, 32 lanes, each node
+// the sum of its two halves). Every lane adds the partner half of its block;
+// IEEE addition is commutative, so the bits are those of the scan.
+__device__ inline double wave_tree_total(double v) {
+    v = v + dpp_d<0xB1>(v);    // quad_perm [1,0,3,2]: the other lane of each pair
+    v = v + dpp_d<0x4E>(v);    // quad_perm [2,3,0,1]: the other pair of each quad
+    v = v + dpp_d<0x141>(v);   // row_half_mirror: a lane of the other quad of each 8
+    v = v + dpp_d<0x140>(v);   // row_mirror: a lane of the other 8 of each row of 16
+    return (read_lane_d(v, 0) + read_lane_d(v, 16)) + (read_lane_d(v, 32) + read_lane_d(v, 48));
+}
+
 // One wavefront per leaf: the leaf's compensated sum, and the plain total of
-// each row of the leaf (64 loads of 16 bytes) from the same wave scan that
-// k_sample runs over a row, so that its running sums over rows can start at
-// any row with the carry a scan from the leaf's start would have there.
+// each row of the leaf (64 loads of 16 bytes), bit for bit the lane-63 value
+// of the wave scan k_sample runs over that row, so that its running sums
+// over rows can start at any row with the carry a scan from the leaf's
+// start would have there.
 template <typename T>
 __global__ __launch_bounds__(256) void k_leafsum(const u4 *__restrict__ psi, int n, double *__restrict__ leafsum,
                                                  double *__restrict__ rowsum) {
@@ -110,8 +147,12 @@ __global__ __launch_bounds__(256) void k_leafsum(const u4 *__restrict__ psi, int
     const u4 *p = psi + leaf * ((1ull << kLeafBits) / E);
     double *rs = rowsum + leaf * kRowsPerLeaf;
     DD acc = dd_zero();
-    for (uint64_t row = 0; row * 64 < nvec; ++row) {
-        const uint64_t vi = row * 64 + lane;
+    double lts[kRowsPerLeaf];   // this lane's part of each row total
+#pragma unroll
+    for (int row = 0; row < kRowsPerLeaf; ++row) {
+        lts[row] = 0.0;
+        if ((uint64_t)row * 64 >= nvec) continue;
+        const uint64_t vi = (uint64_t)row * 64 + lane;
         Q q;
         q.v = u4{0, 0, 0, 0};
         if (vi < nvec) q.v = ld_nt(p + vi);
@@ -122,8 +163,13 @@ __global__ __launch_bounds__(256) void k_leafsum(const u4 *__restrict__ psi, int
             if (vi < nvec) neum_add(acc, pr);
             lt += pr;
         }
-        const double incl = wave_incl_scan(lt, lane);
-        if (lane == 63) rs[row] = incl;
+        lts[row] = lt;
+    }
+#pragma unroll
+    for (int row = 0; row < kRowsPerLeaf; ++row) {
+        if ((uint64_t)row * 64 >= nvec) continue;
+        const double t = wave_tree_total(lts[row]);
+        if (lane == 0) rs[row] = t;
     }
     acc = wave_reduce_dd(acc, lane);
     if (lane == 0) leafsum[leaf] = dd_value(acc);
@@ -215,16 +261,6 @@ __global__ __launch_bounds__(kScanThreads) void k_leaf_scan(const double *__rest
 }
 
 // ---- shot resolution ---------------------------------------------------
-__device__ inline double read_lane_d(double v, int l) {
-    union {
-        double d;
-        int w[2];
-    } u;
-    u.d = v;
-    u.w[0] = __builtin_amdgcn_readlane(u.w[0], l);
-    u.w[1] = __builtin_amdgcn_readlane(u.w[1], l);
-    return u.d;
-}
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_sample(const u4 *__restrict__ psi, int n, const double *__restrict__ leafcdf,
