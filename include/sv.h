@@ -250,9 +250,10 @@ sv_status sv_sample(sv_state st, int64_t shots, uint64_t seed, uint64_t *out);
  * takes slot floor(u1 N) and returns the slot if u2 < prob[slot], else its
  * alias. out (caller-owned, `shots` entries) receives the outcomes; prob_out
  * and alias_out (nullable, N entries each, caller-owned) receive the table.
- * The table and its build scratch, 40 bytes per amplitude (and under 0.1%
+ * The table and its build scratch, 36 bytes per amplitude (and under 0.1%
  * more), are taken from the arena for the call (SV_E_OOM if they do not
- * fit). Synchronous. */
+ * fit); states of more than 32 qubits, whose table cannot fit next to them
+ * on one device, give SV_E_INVALID. Synchronous. */
 sv_status sv_sample_alias(sv_state st, int64_t shots, uint64_t seed, uint64_t *out, double *prob_out,
                           uint64_t *alias_out);
 

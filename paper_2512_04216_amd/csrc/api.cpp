@@ -850,6 +850,7 @@ sv_status sv_sample_alias(sv_state st, int64_t shots, uint64_t seed, uint64_t *o
                           uint64_t *alias_out) {
     if (!st || shots < 0) return fail(SV_E_INVALID, "bad argument");
     if (shots > 0 && !out) return fail(SV_E_INVALID, "null output");
+    if (st->n > 32) return fail(SV_E_INVALID, "alias tables hold at most 2^32 outcomes (32 qubits)");
     sv_ctx c = st->ctx;
     const uint64_t N = 1ull << st->n;
     void *aws = c->arena.alloc(svk::alias_workspace_bytes(st->n));
@@ -857,7 +858,7 @@ sv_status sv_sample_alias(sv_state st, int64_t shots, uint64_t seed, uint64_t *o
     sv_status r = SV_OK;
     hipError_t e;
     {
-        TraceScope ts(&c->tracer, st->stream, "alias_build", 41.0 * N + (double)st->bytes * 3.0);
+        TraceScope ts(&c->tracer, st->stream, "alias_build", 37.0 * N + (double)st->bytes * 3.0);
         e = svk::launch_alias_build(st->psi, st->n, st->is_c64(), st->ws, aws, st->stream);
     }
     double total = 0;

@@ -169,17 +169,19 @@ union WriteStage {
     DD pre[kTile];
 };
 
-// Per-entry prefixes, compacted: lights in index order at [0, nl), heavies at
-// [nl, N). Each thread walks its contiguous amplitudes and stages the light
-// and heavy entries in LDS at their ranks within the tile (lights first);
-// the tile's two runs, its prob values and identity aliases are then stored
-// coalesced.
+// Per-entry prefixes and outcome indices, compacted: lights in index order
+// at [0, nl), heavies at [nl, N). Each thread walks its contiguous amplitudes
+// and stages the light and heavy entries in LDS at their ranks within the
+// tile (lights first); the tile's two runs, its prob values and identity
+// aliases are then stored coalesced. Indices take 4 bytes: a table of more
+// than 2^32 entries (36 B each) does not fit next to its state on one device,
+// and the entry point rejects it.
 template <typename T>
 __global__ __launch_bounds__(kT) void k_alias_write(const u4 *__restrict__ psi, int n,
                                                     const double *__restrict__ norm2, const Acc *__restrict__ rec,
                                                     const Acc *__restrict__ grp, const uint64_t *__restrict__ meta,
                                                     double *__restrict__ prob, uint64_t *__restrict__ alias,
-                                                    uint64_t *__restrict__ idx, DD *__restrict__ pre) {
+                                                    uint32_t *__restrict__ idx, DD *__restrict__ pre) {
     __shared__ double s_lds[kTile];
     __shared__ uint16_t l_idx[kTile];
     __shared__ WriteStage st;
@@ -218,7 +220,7 @@ __global__ __launch_bounds__(kT) void k_alias_write(const u4 *__restrict__ psi, 
     const uint64_t gl = tile_off.nl, gh = nl + (t0 - tile_off.nl);   // where the tile's runs start
     for (int v = threadIdx.x; v < cnt; v += kT) {
         const uint64_t r = v < tile_nl ? gl + (uint64_t)v : gh + (uint64_t)(v - tile_nl);
-        idx[r] = t0 + l_idx[v];
+        idx[r] = (uint32_t)(t0 + l_idx[v]);
         pre[r] = st.pre[v];
         prob[t0 + v] = s_lds[v];
         alias[t0 + v] = t0 + v;
@@ -252,7 +254,7 @@ __global__ __launch_bounds__(kT) void k_alias_part(uint64_t N, const uint64_t *_
 // search in LDS. Light i sets the alias of light i + 1 (light 0 takes heavy 0).
 __global__ __launch_bounds__(kT) void k_alias_merge(uint64_t N, const uint64_t *__restrict__ meta,
                                                     const uint64_t *__restrict__ part,
-                                                    const uint64_t *__restrict__ idx, const DD *__restrict__ pre,
+                                                    const uint32_t *__restrict__ idx, const DD *__restrict__ pre,
                                                     double *__restrict__ prob, uint64_t *__restrict__ alias) {
     __shared__ DD lds[kMerge];
     const uint64_t nl = meta[0], nh = N - nl;
@@ -334,7 +336,7 @@ AliasLayout layout(int n) {
     L.prob = 0;
     L.alias = L.prob + 8 * N;
     L.idx = L.alias + 8 * N;
-    L.pre = L.idx + 8 * N;
+    L.pre = (L.idx + 4 * N + 255) & ~255ull;
     L.rec = L.pre + 16 * N;
     L.grp = L.rec + ((sizeof(Acc) * ntiles + 255) & ~255ull);
     L.part = L.grp + ((sizeof(Acc) * ngroups(ntiles) + 255) & ~255ull);
@@ -374,7 +376,8 @@ hipError_t launch_alias_build(const void *psi, int n, int is_c64, void *ws, void
     hipLaunchKernelGGL(k_alias_scan_grp, dim3((unsigned)ng), dim3(kScanT), 0, s, rec, ntiles, grp);
     hipLaunchKernelGGL(k_alias_scan, dim3(1), dim3(kScanT), 0, s, grp, ng, meta);
     double *prob = (double *)(w + L.prob);
-    uint64_t *alias = (uint64_t *)(w + L.alias), *idx = (uint64_t *)(w + L.idx);
+    uint64_t *alias = (uint64_t *)(w + L.alias);
+    uint32_t *idx = (uint32_t *)(w + L.idx);
     DD *pre = (DD *)(w + L.pre);
     if (is_c64)
         hipLaunchKernelGGL(k_alias_write<float>, dim3((unsigned)ntiles), dim3(kT), 0, s, (const u4 *)psi, n, norm2,

@@ -179,8 +179,8 @@ struct PackedBatch {
 
 // ---- Walker alias tables ----
 // Device workspace of an alias table of n qubits: prob (FP64) and alias
-// (uint64) per outcome first, then the build's scratch (24 B per outcome and
-// a few bytes per 2048 outcomes): 40 B per outcome in all.
+// (uint64) per outcome first, then the build's scratch (20 B per outcome and
+// a few bytes per 2048 outcomes): 36 B per outcome in all. n <= 32.
 uint64_t alias_workspace_bytes(int n);
 const double *alias_prob(const void *aws);
 const uint64_t *alias_alias(const void *aws, int n);
