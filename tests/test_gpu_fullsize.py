@@ -99,6 +99,15 @@ def test_fused_cross_mirror_full_size(big_ctx, S, n, dtype, fuse_k):
     assert 1.0 - abs(a0) ** 2 <= tol
 
 
+def test_alias_rejects_more_than_32_qubits(big_ctx, S):
+    # a table of 2^33 outcomes (36 B each) cannot fit next to its state; the
+    # call fails with SV_E_INVALID before it allocates, and the state stays usable
+    with S.State(big_ctx, 33, "c64") as st:
+        with pytest.raises(S.SvError):
+            st.sample_alias(10, 1)
+        assert st.sample(4, 1).tolist() == [0, 0, 0, 0]
+
+
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_sampling_28q_coupled_to_oracle(ctx, S, O, dtype):
     # the inverse-CDF sampler at the measured size and shot count (4096 shots
