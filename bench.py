@@ -15,7 +15,7 @@ The JSON line also carries:
   cpu_baseline -- the plain complex128 CPU oracle timed on a bounded prefix of the
                   same brickwork circuit (single thread).
 
---gpus N with N > 1 exits: this build runs on one GPU.
+--gpus N with N > 1 exits: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -659,7 +659,7 @@ def main():
                     help="state sizes of the sampling comparison")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only (no sharding or collectives); use --gpus 1",
+        print("bench.py: the library runs on one GPU only (no sharding or collectives); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 

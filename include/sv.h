@@ -48,7 +48,7 @@ typedef enum {
     SV_E_NUMERIC = -4,      /* non-finite matrix entry, or a zero-norm state */
     SV_E_NOTFOUND = -5,     /* unknown request id */
     SV_E_BUSY = -6,         /* the server queue is full */
-    SV_E_UNSUPPORTED = -7   /* valid request outside what this build implements */
+    SV_E_UNSUPPORTED = -7   /* valid request outside what the library implements */
 } sv_status;
 
 typedef enum { SV_C64 = 0, SV_C128 = 1 } sv_dtype;
